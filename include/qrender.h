@@ -1,0 +1,256 @@
+/*
+ * qrender.h - C ABI of the Quantile Rendering library for AMD MI355X (gfx950).
+ *
+ * Renders per-Gaussian feature vectors (up to 512-D and beyond) of a set of
+ * 3D Gaussians into [H, W, D] feature maps, either with the dense front-to-back
+ * alpha blend of every Gaussian on each pixel's ray (Eq. 1 of Jeong et al.,
+ * "Quantile Rendering: Efficiently Embedding High-dimensional Feature on 3D
+ * Gaussian Splatting", Sec. 3) or with Quantile Rendering (Algorithm 1,
+ * Sec. 4.2), which blends only the <= K Gaussians whose step in transmittance
+ * crosses one of the thresholds t_m = 1 - m/(K+1) and normalises by 1 - T^Q.
+ *
+ * Pipeline (all calls asynchronous on the caller's HIP stream):
+ *   qr_project -> qr_bin_sort -> qr_render_dense | qr_render_quantile
+ *   (+ qr_render_*_backward for gradients).
+ *
+ * Conventions shared by every entry point:
+ *  - Every array argument is a DEVICE pointer owned by the caller, unless
+ *    marked "host". The library never allocates, frees or retains memory;
+ *    scratch space is passed in as a caller-owned workspace.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Kernels are enqueued on it and the call returns without waiting, except
+ *    where a call says it synchronises.
+ *  - The return value is a qr_status. On QR_ERR_INVALID_ARG or
+ *    QR_ERR_UNSUPPORTED nothing has been launched and no output is written.
+ *    QR_ERR_HIP means a launch failed; outputs are then undefined.
+ *    qr_last_error() returns a message describing the last failure of the
+ *    calling thread.
+ *  - Arrays are dense and row-major; "f32[N,4]" is N rows of 4 floats.
+ *  - Screen tiles are 16 x 16 pixels, tile id = ty * tiles_x + tx with
+ *    tiles_x = ceil(W / 16), tiles_y = ceil(H / 16). Pixel (px, py) is
+ *    sampled at its centre (px + 0.5, py + 0.5). Feature maps are pixel-major
+ *    [H, W, D] float32.
+ *  - The library is stateless and thread-safe; calls on different streams
+ *    may run concurrently when their outputs do not overlap.
+ */
+#ifndef QRENDER_H
+#define QRENDER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QR_TILE 16
+#define QR_MAX_K 32        /* largest number of quantile Gaussians per ray */
+#define QR_MAX_DIM 4096    /* largest feature width D */
+
+typedef enum qr_status {
+  QR_OK = 0,
+  QR_ERR_INVALID_ARG = -1, /* null pointer, non-positive size, bad range */
+  QR_ERR_UNSUPPORTED = -2, /* dtype, D not a multiple of 16, K out of range */
+  QR_ERR_CAPACITY = -3,    /* workspace or pair capacity too small */
+  QR_ERR_HIP = -4          /* a HIP runtime call or launch failed */
+} qr_status;
+
+/* Storage type of the feature table F [N, D]. Blending always accumulates in
+ * float32; reduced types are decoded to float32 when loaded. */
+typedef enum qr_dtype {
+  QR_F32 = 0,      /* float32 */
+  QR_BF16 = 1,     /* bfloat16 (upper half of a float32) */
+  QR_FP8_E4M3 = 2  /* OCP FP8 e4m3 code times a per-Gaussian float32 scale */
+} qr_dtype;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward). A world point X
+ * maps to camera space as R_cw X + t (R_cw row-major). Gaussians whose
+ * camera-space depth is <= z_near are culled. */
+typedef struct qr_camera {
+  float R_cw[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float z_near;
+} qr_camera;
+
+/* Rasterisation constants (the 3D-GS conventions the paper renders with):
+ *  alpha_min  a Gaussian is on a pixel's ray list only where alpha' >= alpha_min
+ *             (typ. 1/255); it also defines the footprint ellipse.
+ *  alpha_max  alpha' = min(alpha_max, o G) (typ. 0.99).
+ *  T_eps      dense blend stops before transmittance falls below T_eps
+ *             (typ. 1e-4; 0 blends every Gaussian on the ray).
+ *  dilation   added to both diagonal entries of the 2D covariance, px^2
+ *             (typ. 0.3).
+ *  guard      x/z and y/z are clamped to guard x the half field of view when
+ *             the projection Jacobian is formed (typ. 1.3). */
+typedef struct qr_params {
+  float alpha_min;
+  float alpha_max;
+  float T_eps;
+  float dilation;
+  float guard;
+} qr_params;
+
+/* Library version string (static storage). */
+const char* qr_version(void);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* qr_last_error(void);
+
+/*
+ * qr_project - EWA splatting of N 3D Gaussians (Sec. 3: Sigma = R S S^T R^T
+ * from scale s and quaternion r; a 2D Gaussian G(u) per pixel).
+ *
+ * Inputs (device): means3d f32[N,3]; scales f32[N,3] (linear, not log);
+ * quats f32[N,4] as (w, x, y, z), normalised inside; opacity f32[N]
+ * (activated, in [0,1]). cam, prm: host pointers.
+ * Outputs (device): means2d f32[N,2] (u, v in pixels); conic_opacity f32[N,4]
+ * = (a, b, c, o) with [[a, b], [b, c]] the inverse 2D covariance; depth f32[N]
+ * (camera-space z); tile_rect i32[N,4] = (tx0, ty0, tx1, ty1), a half-open
+ * tile rectangle covering every pixel where alpha' >= alpha_min (the bounding
+ * box of the ellipse d^T conic d <= 2 ln(o / alpha_min)); tiles_touched
+ * u32[N] = tile count of the rectangle. Culled Gaussians (behind z_near,
+ * o < alpha_min, singular covariance, off screen, non-finite input) get
+ * tiles_touched = 0 and an empty rectangle.
+ * N = 0 is valid and launches nothing.
+ */
+int qr_project(void* stream, int64_t n,
+               const float* means3d, const float* scales, const float* quats,
+               const float* opacity, const qr_camera* cam, const qr_params* prm,
+               float* means2d, float* conic_opacity, float* depth,
+               int32_t* tile_rect, uint32_t* tiles_touched);
+
+/*
+ * qr_count_pairs - total number of (tile, Gaussian) pairs, sum of
+ * tiles_touched. SYNCHRONISES the stream. `workspace` must hold at least
+ * 8 bytes (device). Writes *total (host).
+ */
+int qr_count_pairs(void* stream, int64_t n, const uint32_t* tiles_touched,
+                   void* workspace, size_t workspace_bytes, uint64_t* total);
+
+/*
+ * qr_bin_sort_workspace_size - bytes of device workspace qr_bin_sort needs for
+ * n Gaussians, a tiles_x x tiles_y grid and room for `capacity` pairs.
+ * Host-only; writes *bytes.
+ */
+int qr_bin_sort_workspace_size(int64_t n, int32_t tiles_x, int32_t tiles_y,
+                               int64_t capacity, size_t* bytes);
+
+/*
+ * qr_bin_sort - per-tile, depth-ordered Gaussian lists (the ordered ray
+ * sequence S_r of Eq. 1, built per tile as in 3D-GS).
+ *
+ * Emits one pair per tile in each tile_rect, keyed (tile id << 32) | bits of
+ * the float32 depth, and sorts the keys with a stable LSD radix sort in
+ * Gaussian-index order, so each tile's list is ordered by (depth, index).
+ * Inputs: tile_rect, tiles_touched, depth as written by qr_project.
+ * Outputs: sorted_gid u32[capacity] (Gaussian index of each sorted pair);
+ * sorted_keys u64[capacity] (nullable; the sorted keys); tile_offsets
+ * u32[tiles_x*tiles_y + 1] with tile t's list at
+ * [tile_offsets[t], tile_offsets[t+1]); total_pairs u32[1] = number of pairs.
+ * If the pair count exceeds `capacity`, the call still succeeds
+ * asynchronously but *total_pairs > capacity and the outputs are invalid:
+ * callers check total_pairs and retry with a larger capacity.
+ * The pair count must stay below 2^32 - 1.
+ */
+int qr_bin_sort(void* stream, int64_t n, int32_t tiles_x, int32_t tiles_y,
+                const int32_t* tile_rect, const uint32_t* tiles_touched,
+                const float* depth, int64_t capacity,
+                void* workspace, size_t workspace_bytes,
+                uint32_t* sorted_gid, uint64_t* sorted_keys,
+                uint32_t* tile_offsets, uint32_t* total_pairs);
+
+/*
+ * qr_render_dense - dense alpha blend of Eq. 1 per pixel:
+ *   alpha'_i = min(alpha_max, o_i exp(-(a dx^2 + 2 b dx dy + c dy^2)/2)),
+ *   entries with alpha'_i < alpha_min are skipped, T_1 = 1,
+ *   out = sum_i T_i alpha'_i f_i, T_{i+1} = T_i (1 - alpha'_i),
+ * stopping before an entry that would take T below T_eps.
+ * Inputs: the tile lists of qr_bin_sort, means2d / conic_opacity of
+ * qr_project, features [N, dim] of type `dtype` (feature_scale f32[N] for
+ * QR_FP8_E4M3, else ignored). dim must be a multiple of 16, <= QR_MAX_DIM.
+ * Outputs: out f32[H,W,dim]; T_final f32[H,W] (nullable); n_contrib
+ * i32[H,W] (nullable; tile-list position + 1 of the last blended entry).
+ */
+int qr_render_dense(void* stream, int32_t width, int32_t height,
+                    const qr_params* prm, const uint32_t* tile_offsets,
+                    const uint32_t* sorted_gid, const float* means2d,
+                    const float* conic_opacity, const void* features,
+                    int32_t dtype, const float* feature_scale, int32_t dim,
+                    float* out, float* T_final, int32_t* n_contrib);
+
+/*
+ * qr_render_quantile - Quantile Rendering, Algorithm 1 per pixel:
+ *   T = 1, T^Q = 1, f^Q = 0, k = 0; for each entry on the ray:
+ *   T_test = T (1 - alpha'); if T_test < t_{k+1}: k += 1, w = T^Q alpha',
+ *   f^Q += w f, T^Q *= 1 - alpha', and k advances past every further
+ *   threshold T_test is below; the walk ends once k = K (equivalently
+ *   T_test < 1/(K+1)); T = T_test. out = f^Q / (1 - T^Q), or 0 if nothing
+ *   was selected. Thresholds t_m = 1 - m/(K+1) are rounded once to float32;
+ *   the comparison is strict.
+ * Inputs as qr_render_dense; 1 <= K <= QR_MAX_K.
+ * Outputs: out f32[H,W,dim]; T_q f32[H,W] (nullable); n_sel i32[H,W]
+ * (nullable; number of selected Gaussians); sel_gid i32[H,W,K] and sel_w
+ * f32[H,W,K] (nullable; selected Gaussian indices in ray order and their
+ * weights w^Q, padded with -1 / 0).
+ */
+int qr_render_quantile(void* stream, int32_t width, int32_t height,
+                       const qr_params* prm, int32_t K,
+                       const uint32_t* tile_offsets, const uint32_t* sorted_gid,
+                       const float* means2d, const float* conic_opacity,
+                       const void* features, int32_t dtype,
+                       const float* feature_scale, int32_t dim,
+                       float* out, float* T_q, int32_t* n_sel,
+                       int32_t* sel_gid, float* sel_w);
+
+/*
+ * qr_render_dense_backward / qr_render_quantile_backward - gradients of the
+ * two renderers given dL/d(out) = grad_out f32[H,W,dim]. The forward walk is
+ * recomputed (same float32 arithmetic, so the same entries are blended or
+ * selected) and transmittance is recovered in a reverse sweep. Discrete
+ * decisions pass no gradient; a clamped alpha' passes none to o or geometry.
+ * Gradients are ACCUMULATED (atomic adds; the caller zeroes them first):
+ * grad_features f32[N,dim] (w.r.t. the decoded float32 features),
+ * grad_means2d f32[N,2], grad_conic_opacity f32[N,4] = d/d(a, b, c, o) with
+ * b the single off-diagonal conic entry. Any gradient pointer may be NULL
+ * to skip it. The dense call also takes its forward output `out`
+ * f32[H,W,dim]: <grad_out, out> per pixel is the sum over the whole ray of
+ * w_i <grad_out, f_i>, from which the tail sums of the gradient are formed in
+ * one front-to-back pass. Other arguments as in the forward calls.
+ */
+int qr_render_dense_backward(void* stream, int32_t width, int32_t height,
+                             const qr_params* prm, const uint32_t* tile_offsets,
+                             const uint32_t* sorted_gid, const float* means2d,
+                             const float* conic_opacity, const void* features,
+                             int32_t dtype, const float* feature_scale,
+                             int32_t dim, const float* out,
+                             const float* grad_out, float* grad_features,
+                             float* grad_means2d, float* grad_conic_opacity);
+
+int qr_render_quantile_backward(void* stream, int32_t width, int32_t height,
+                                const qr_params* prm, int32_t K,
+                                const uint32_t* tile_offsets,
+                                const uint32_t* sorted_gid,
+                                const float* means2d, const float* conic_opacity,
+                                const void* features, int32_t dtype,
+                                const float* feature_scale, int32_t dim,
+                                const float* grad_out, float* grad_features,
+                                float* grad_means2d, float* grad_conic_opacity);
+
+/*
+ * qr_quantize_features - encodes a float32 feature table f32[N,dim] for
+ * storage: QR_BF16 writes u16[N,dim] (round to nearest even); QR_FP8_E4M3
+ * writes u8[N,dim] OCP e4m3 codes of f / s_i (nearest, ties to even,
+ * |value| <= 448) and scale f32[N] with s_i = max_d |f_id| / 448 (1 for an
+ * all-zero row). `scale` is ignored for QR_BF16.
+ */
+int qr_quantize_features(void* stream, int64_t n, int32_t dim,
+                         const float* features, int32_t dtype, void* out,
+                         float* scale);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QRENDER_H */

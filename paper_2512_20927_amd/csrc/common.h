@@ -1,0 +1,67 @@
+// Internal helpers shared by the HIP sources of the library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "qrender.h"
+
+namespace qr {
+
+constexpr int kTile = QR_TILE;
+constexpr int kTilePix = QR_TILE * QR_TILE;  // 256 pixels, one per thread
+constexpr int kWave = 64;
+
+// ---- error reporting (thread-local, host) ---------------------------------
+void set_error(const char* fmt, ...);
+int fail(int code, const char* fmt, ...);
+int check_launch(const char* what);
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---- feature decoding -----------------------------------------------------
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+
+// OCP e4m3 code -> float32, from the format definition: bias 7, three
+// mantissa bits, subnormals at exponent 0. The 7-bit magnitude is placed in
+// the float32 exponent/mantissa fields and rebiased by a multiply by 2^120;
+// the subnormal case is handled explicitly so that no float32 denormal is
+// ever formed. Code 0x7F/0xFF (NaN) never occurs in encoded tables.
+__device__ __forceinline__ float e4m3_to_f32(uint32_t code) {
+  const uint32_t mag = code & 0x7Fu;
+  const uint32_t e = mag >> 3;
+  float v;
+  if (e == 0) {
+    v = static_cast<float>(mag) * 0.001953125f;  // m * 2^-9
+  } else {
+    v = __uint_as_float((mag + (120u << 3)) << 20);  // (e+120) exponent, m mantissa
+  }
+  return (code & 0x80u) ? -v : v;
+}
+
+// Loads 4 consecutive features (d .. d+3, d % 4 == 0) of row g as float32.
+template <int DT>
+__device__ __forceinline__ float4 load_feat4(const void* __restrict__ feats,
+                                             const float* __restrict__ scale,
+                                             int64_t g, int dim, int d) {
+  if constexpr (DT == QR_F32) {
+    return *reinterpret_cast<const float4*>(static_cast<const float*>(feats) + g * dim + d);
+  } else if constexpr (DT == QR_BF16) {
+    const uint2 r = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(feats) + g * dim + d);
+    return make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xFFFF0000u),
+                       __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xFFFF0000u));
+  } else {
+    const uint32_t r = *reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(feats) + g * dim + d);
+    const float s = scale[g];
+    return make_float4(e4m3_to_f32(r & 0xFFu) * s, e4m3_to_f32((r >> 8) & 0xFFu) * s,
+                       e4m3_to_f32((r >> 16) & 0xFFu) * s, e4m3_to_f32(r >> 24) * s);
+  }
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace qr

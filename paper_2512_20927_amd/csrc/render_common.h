@@ -1,0 +1,86 @@
+// Helpers shared by the forward and backward renderers.
+#pragma once
+
+#include "common.h"
+
+namespace qr {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
+// with a private L2. Remap so that XCD x receives a contiguous run of tiles:
+// neighbouring tiles share most of their Gaussians (records and feature
+// rows), which then hit the same L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  constexpr int kXcd = 8;
+  const int xcd = bid % kXcd;
+  const int slot = bid / kXcd;
+  const int per = nblocks / kXcd;
+  const int rem = nblocks % kXcd;
+  return xcd * per + min(xcd, rem) + slot;
+}
+
+// t_m = 1 - m/(K+1) evaluated in double and rounded once to float;
+// m = K+1 gives 0, a threshold no transmittance falls below.
+__device__ __forceinline__ float quantile_threshold(int m, int K) {
+  return static_cast<float>(1.0 - static_cast<double>(m) / static_cast<double>(K + 1));
+}
+
+// alpha' = min(alpha_max, o exp(power)), power = -(a dx^2 + 2 b dx dy + c dy^2)/2,
+// with every multiply-add written out so that forward and backward kernels
+// evaluate bit-identical values.
+struct AlphaEval {
+  float alpha, G, dx, dy;
+  bool clamped;
+};
+
+__device__ __forceinline__ AlphaEval eval_alpha(float2 mean, float4 co, float pxc, float pyc,
+                                                float alpha_max) {
+  AlphaEval r;
+  r.dx = pxc - mean.x;
+  r.dy = pyc - mean.y;
+  const float cross2 = ((2.f * co.y) * r.dx) * r.dy;  // products only: nothing to contract
+  const float q = fmaf(co.x * r.dx, r.dx, fmaf(co.z * r.dy, r.dy, cross2));
+  r.G = expf(-0.5f * q);
+  const float raw = co.w * r.G;
+  r.clamped = raw >= alpha_max;
+  r.alpha = r.clamped ? alpha_max : raw;
+  return r;
+}
+
+__device__ __forceinline__ float gauss_alpha(float2 mean, float4 co, float pxc, float pyc,
+                                             float alpha_max) {
+  return eval_alpha(mean, co, pxc, pyc, alpha_max).alpha;
+}
+
+__device__ __forceinline__ void store_stream(float4* p, float4 v) {
+  f32x4 x = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(x, reinterpret_cast<f32x4*>(p));
+}
+
+// Host-side validation shared by the render entry points.
+inline int validate_render(const char* name, int32_t width, int32_t height, const qr_params* prm,
+                           const uint32_t* tile_offsets, const uint32_t* sorted_gid,
+                           const float* means2d, const float* conic_opacity, const void* features,
+                           int32_t dtype, const float* feature_scale, int32_t dim,
+                           const void* out) {
+  if (width <= 0 || height <= 0) return fail(QR_ERR_INVALID_ARG, "%s: image size must be positive", name);
+  if (static_cast<int64_t>(ceil_div(width, kTile)) * ceil_div(height, kTile) >= (1ll << 31))
+    return fail(QR_ERR_UNSUPPORTED, "%s: image too large", name);
+  if (!prm) return fail(QR_ERR_INVALID_ARG, "%s: null params", name);
+  if (!(prm->alpha_min > 0.f) || !(prm->alpha_max >= prm->alpha_min) || !(prm->alpha_max < 1.f))
+    return fail(QR_ERR_INVALID_ARG, "%s: need 0 < alpha_min <= alpha_max < 1", name);
+  if (!(prm->T_eps >= 0.f)) return fail(QR_ERR_INVALID_ARG, "%s: T_eps must be >= 0", name);
+  if (!tile_offsets || !sorted_gid || !means2d || !conic_opacity || !features || !out)
+    return fail(QR_ERR_INVALID_ARG, "%s: null array pointer", name);
+  if (dtype != QR_F32 && dtype != QR_BF16 && dtype != QR_FP8_E4M3)
+    return fail(QR_ERR_UNSUPPORTED, "%s: unknown feature dtype %d", name, dtype);
+  if (dtype == QR_FP8_E4M3 && !feature_scale)
+    return fail(QR_ERR_INVALID_ARG, "%s: FP8 features need a per-Gaussian scale", name);
+  if (dim <= 0 || dim % 16 != 0 || dim > QR_MAX_DIM)
+    return fail(QR_ERR_UNSUPPORTED, "%s: dim = %d must be a positive multiple of 16 <= %d", name,
+                dim, QR_MAX_DIM);
+  return QR_OK;
+}
+
+}  // namespace qr

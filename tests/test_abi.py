@@ -1,0 +1,130 @@
+"""The C-ABI library loads on a machine without a GPU, exports every entry
+point include/qrender.h declares, and rejects bad arguments on the host
+before any HIP call (no compute call is made here)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qrender.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qr_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2512_20927_amd import _lib
+    return _lib
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(L.lib(), n), n
+    assert sorted(L.EXPORTED) == names
+
+
+def test_version(L):
+    assert L.version().startswith("qrender")
+
+
+def _err(L, rc):
+    return rc, L.last_error()
+
+
+def test_project_validation(L):
+    lib = L.lib()
+    cam = L.make_camera(type("C", (), dict(R_cw=[1, 0, 0, 0, 1, 0, 0, 0, 1], t=[0, 0, 3], fx=50.0,
+                                             fy=50.0, cx=32.0, cy=32.0, width=64, height=64,
+                                             z_near=0.2))())
+    prm = L.make_params()
+    nul = None
+    rc, msg = _err(L, lib.qr_project(nul, -1, nul, nul, nul, nul, ctypes.byref(cam), ctypes.byref(prm), nul, nul, nul, nul, nul))
+    assert rc == L.QR_ERR_INVALID_ARG and "n < 0" in msg
+    rc, msg = _err(L, lib.qr_project(nul, 10, nul, nul, nul, nul, ctypes.byref(cam), ctypes.byref(prm), nul, nul, nul, nul, nul))
+    assert rc == L.QR_ERR_INVALID_ARG and "null" in msg
+    rc, _ = _err(L, lib.qr_project(nul, 10, nul, nul, nul, nul, None, ctypes.byref(prm), nul, nul, nul, nul, nul))
+    assert rc == L.QR_ERR_INVALID_ARG
+    bad = L.make_camera(type("C", (), dict(R_cw=[1, 0, 0, 0, 1, 0, 0, 0, 1], t=[0, 0, 3], fx=-1.0,
+                                             fy=50.0, cx=32.0, cy=32.0, width=64, height=64))())
+    rc, msg = _err(L, lib.qr_project(nul, 10, nul, nul, nul, nul, ctypes.byref(bad), ctypes.byref(prm), nul, nul, nul, nul, nul))
+    assert rc == L.QR_ERR_INVALID_ARG and "focal" in msg
+    badp = L.make_params(alpha_min=0.0)
+    rc, _ = _err(L, lib.qr_project(nul, 10, nul, nul, nul, nul, ctypes.byref(cam), ctypes.byref(badp), nul, nul, nul, nul, nul))
+    assert rc == L.QR_ERR_INVALID_ARG
+    # n = 0 is a valid no-op
+    assert lib.qr_project(nul, 0, nul, nul, nul, nul, ctypes.byref(cam), ctypes.byref(prm), nul, nul, nul, nul, nul) == L.QR_OK
+
+
+def test_bin_sort_validation_and_workspace_size(L):
+    lib = L.lib()
+    out = ctypes.c_size_t(0)
+    assert lib.qr_bin_sort_workspace_size(1000, 4, 4, 5000, ctypes.byref(out)) == L.QR_OK
+    small = out.value
+    assert lib.qr_bin_sort_workspace_size(1000, 4, 4, 50000, ctypes.byref(out)) == L.QR_OK
+    assert out.value > small > 5000 * 24
+    assert lib.qr_bin_sort_workspace_size(-1, 4, 4, 10, ctypes.byref(out)) == L.QR_ERR_INVALID_ARG
+    assert lib.qr_bin_sort_workspace_size(10, 0, 4, 10, ctypes.byref(out)) == L.QR_ERR_INVALID_ARG
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    rc = lib.qr_bin_sort(None, 1000, 4, 4, dummy, dummy, dummy, 5000, dummy, 16, dummy, None, dummy, dummy)
+    assert rc == L.QR_ERR_CAPACITY and "workspace" in L.last_error()
+    rc = lib.qr_bin_sort(None, 1000, 4, 4, None, dummy, dummy, 5000, dummy, 1 << 30, dummy, None, dummy, dummy)
+    assert rc == L.QR_ERR_INVALID_ARG
+    rc = lib.qr_bin_sort(None, 1 << 33, 4, 4, dummy, dummy, dummy, 5000, dummy, 1 << 30, dummy, None, dummy, dummy)
+    assert rc == L.QR_ERR_UNSUPPORTED
+
+
+def test_render_validation(L):
+    lib = L.lib()
+    prm = L.make_params()
+    d = ctypes.c_void_p(0x1000)
+    P = ctypes.byref(prm)
+    q = lambda W, H, K, dt, sc, dim, sg=None, sw=None: lib.qr_render_quantile(
+        None, W, H, P, K, d, d, d, d, d, dt, sc, dim, d, None, None, sg, sw)
+    assert q(0, 64, 8, 0, None, 16) == L.QR_ERR_INVALID_ARG
+    assert q(64, 64, 0, 0, None, 16) == L.QR_ERR_UNSUPPORTED
+    assert q(64, 64, 33, 0, None, 16) == L.QR_ERR_UNSUPPORTED
+    assert q(64, 64, 8, 0, None, 24) == L.QR_ERR_UNSUPPORTED
+    assert q(64, 64, 8, 0, None, 0) == L.QR_ERR_UNSUPPORTED
+    assert q(64, 64, 8, 7, None, 16) == L.QR_ERR_UNSUPPORTED
+    assert q(64, 64, 8, 2, None, 16) == L.QR_ERR_INVALID_ARG  # fp8 without scale
+    assert q(64, 64, 8, 0, None, 16, sg=d) == L.QR_ERR_INVALID_ARG  # sel_gid without sel_w
+    rc = lib.qr_render_dense(None, 64, 64, P, d, d, d, d, None, 0, None, 16, d, None, None)
+    assert rc == L.QR_ERR_INVALID_ARG
+    rc = lib.qr_render_dense(None, 64, 64, None, d, d, d, d, d, 0, None, 16, d, None, None)
+    assert rc == L.QR_ERR_INVALID_ARG
+    rc = lib.qr_render_dense_backward(None, 64, 64, P, d, d, d, d, d, 0, None, 20, d, d, d, d, d)
+    assert rc == L.QR_ERR_UNSUPPORTED
+    rc = lib.qr_render_quantile_backward(None, 64, 64, P, 40, d, d, d, d, d, 0, None, 16, d, d, d, d)
+    assert rc == L.QR_ERR_UNSUPPORTED
+    rc = lib.qr_quantize_features(None, 10, 16, d, 0, d, None)
+    assert rc == L.QR_ERR_UNSUPPORTED
+    rc = lib.qr_quantize_features(None, 10, 16, d, 2, d, None)
+    assert rc == L.QR_ERR_INVALID_ARG
+
+
+def test_count_pairs_validation(L):
+    lib = L.lib()
+    out = ctypes.c_uint64(7)
+    assert lib.qr_count_pairs(None, 0, None, None, 0, ctypes.byref(out)) == L.QR_OK and out.value == 0
+    d = ctypes.c_void_p(0x1000)
+    assert lib.qr_count_pairs(None, 5, d, d, 4, ctypes.byref(out)) == L.QR_ERR_CAPACITY
+    assert lib.qr_count_pairs(None, 5, None, d, 8, ctypes.byref(out)) == L.QR_ERR_INVALID_ARG
+
+
+def test_product_path_does_not_touch_the_oracle():
+    """The package sources never import, load or run anything under oracle/."""
+    pkg = os.path.join(ROOT, "paper_2512_20927_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"\boracle\b", src), f
