@@ -126,10 +126,14 @@ def cpu_reference(sc, cam, K, budget_s, gpu_out=None, gpu_bins=None):
     n_tiles = tx * ty
     order = [int(x) for x in np.random.default_rng(0).permutation(n_tiles)]
     feats = sc.features
-    # a 4-tile probe sizes the sample to the time budget, then one oracle call
+    # a 4-tile probe (its full-frame output allocation timed apart) sizes the
+    # sample to the time budget, then one oracle call renders the sample
+    t0 = time.perf_counter()
+    np.full((cam.height, cam.width, feats.shape[1]), np.nan)
+    t_alloc = time.perf_counter() - t0
     t0 = time.perf_counter()
     oracle.render_quantile(pr, gids, offs, feats, cam.width, cam.height, K, tiles=order[:4])
-    per_tile = (time.perf_counter() - t0) / 4
+    per_tile = max(time.perf_counter() - t0 - t_alloc, 1e-6) / 4
     left = budget_s - t_proj - t_bin - 4 * per_tile
     n_s = int(min(n_tiles, max(8, left / max(per_tile, 1e-6))))
     t0 = time.perf_counter()

@@ -64,4 +64,26 @@ __device__ __forceinline__ float4 load_feat4(const void* __restrict__ feats,
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Exclusive scan of one value per thread across a 256-thread workgroup (four
+// wave64s): shuffle scan inside each wave, wave totals through `lds4` (four
+// words of LDS). Optionally returns the workgroup total. Contains barriers:
+// every thread of the workgroup must call it.
+__device__ __forceinline__ uint32_t block_scan_exclusive(uint32_t v, uint32_t* lds4,
+                                                         uint32_t* total) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  uint32_t inc = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += t;
+  }
+  if (lane == 63) lds4[wave] = inc;
+  __syncthreads();
+  uint32_t wave_base = 0;
+  for (int w = 0; w < wave; ++w) wave_base += lds4[w];
+  if (total) *total = lds4[0] + lds4[1] + lds4[2] + lds4[3];
+  __syncthreads();
+  return wave_base + inc - v;
+}
+
 }  // namespace qr

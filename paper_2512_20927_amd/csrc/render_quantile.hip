@@ -8,11 +8,11 @@
 // LDS. A pixel is done once all K thresholds are consumed (the paper's stop
 // test T_test < 1/(K+1) is the same event), and the whole workgroup leaves the
 // list as soon as every pixel is done.
-// Phase 2 (gather-blend): each wave takes one pixel at a time, its lanes
-// spanning the feature dimension; the <= K selected feature rows are read
-// (mostly from L2: neighbouring pixels select the same Gaussians) and
-// accumulated in float32, scaled by 1 / (1 - T^Q), and streamed to the
-// [H, W, D] map with non-temporal stores. The map write is the dominant HBM
+// Phase 2 (gather-blend): each wave takes four pixels at a time, its lanes
+// spanning the feature dimension; the <= K selected feature rows of all four
+// are requested together (mostly L2 hits: neighbouring pixels select the same
+// Gaussians), accumulated in float32, scaled by 1 / (1 - T^Q), and streamed
+// to the [H, W, D] map with non-temporal stores. The map write is the dominant HBM
 // traffic of the whole pipeline.
 #include "common.h"
 #include "render_common.h"
@@ -100,30 +100,57 @@ render_quantile_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm, in
   s_inv[tid] = ns > 0 ? 1.f / (1.f - TQ) : 0.f;
   __syncthreads();
 
-  // Phase 2: wave-per-pixel gather of the selected rows, lanes across D.
+  // Phase 2: gather-blend. Wave w owns pixels [64 w, 64 w + 64) and takes
+  // them kPG at a time; lanes span the feature dimension. Every selected row
+  // of the kPG pixels is requested before any is accumulated (rows of pixels
+  // with fewer selections are padded with weight 0 and a valid row of the
+  // group), so each lane keeps 2 kPG independent loads in flight.
+  constexpr int kPG = 4;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int dim4 = dim >> 2;
-  for (int p = wave; p < kTilePix; p += 4) {
-    const int n = s_ns[p];
-    if (n < 0) continue;
-    const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
-    float4* dst = reinterpret_cast<float4*>(out + (static_cast<int64_t>(gy) * W + gx) * dim);
-    const int* gl = s_sel_gid + p * K;
-    const float* wl = s_sel_w + p * K;
-    const float inv = s_inv[p];
-    for (int c = lane; c < dim4; c += 64) {
-      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-      for (int j = 0; j < n; ++j) {
-        const float4 f = load_feat4<DT>(feats, scale, gl[j], dim, 4 * c);
-        const float w = wl[j];
-        acc.x += w * f.x;
-        acc.y += w * f.y;
-        acc.z += w * f.z;
-        acc.w += w * f.w;
+  for (int p0 = wave * 64; p0 < wave * 64 + 64; p0 += kPG) {
+    int n[kPG];
+    int nmax = 0, safe = 0;
+#pragma unroll
+    for (int q = 0; q < kPG; ++q) {
+      n[q] = s_ns[p0 + q];
+      if (n[q] > nmax) {
+        nmax = n[q];
+        safe = s_sel_gid[(p0 + q) * K];
       }
-      acc.x *= inv; acc.y *= inv; acc.z *= inv; acc.w *= inv;
-      store_stream(dst + c, acc);
+    }
+    for (int c = lane; c < dim4; c += 64) {
+      float4 acc[kPG];
+#pragma unroll
+      for (int q = 0; q < kPG; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int j = 0; j < nmax; ++j) {
+        float4 f[kPG];
+        float w[kPG];
+#pragma unroll
+        for (int q = 0; q < kPG; ++q) {
+          const bool ok = j < n[q];
+          const int g = ok ? s_sel_gid[(p0 + q) * K + j] : safe;
+          w[q] = ok ? s_sel_w[(p0 + q) * K + j] : 0.f;
+          f[q] = load_feat4<DT>(feats, scale, g, dim, 4 * c);
+        }
+#pragma unroll
+        for (int q = 0; q < kPG; ++q) {
+          acc[q].x += w[q] * f[q].x;
+          acc[q].y += w[q] * f[q].y;
+          acc[q].z += w[q] * f[q].z;
+          acc[q].w += w[q] * f[q].w;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kPG; ++q) {
+        if (n[q] < 0) continue;  // outside the image
+        const int p = p0 + q;
+        const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
+        float4* dst = reinterpret_cast<float4*>(out + (static_cast<int64_t>(gy) * W + gx) * dim);
+        const float inv = s_inv[p];
+        store_stream(dst + c, make_float4(acc[q].x * inv, acc[q].y * inv, acc[q].z * inv, acc[q].w * inv));
+      }
     }
   }
 }

@@ -1,0 +1,166 @@
+"""GPU backward passes (through the C ABI and through the autograd wrappers)
+against the FP64 oracle's analytic gradients, which the CPU suite pins by
+central finite differences.
+
+The oracle is fed the GPU's projected float32 records and bins. Pixels with a
+discrete decision within 1e-4 (relative) of its boundary may select or blend
+differently in float32; their incoming gradient is set to zero on both sides
+so that they do not enter the comparison. Tolerance: relative L2 error per
+gradient group <= 1e-3 (float32 kernel with atomics vs float64).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.parity_util import DECISION_WINDOW, proj_for_oracle
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def qr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_20927_amd as qr
+    return qr
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _setup(qr, sc, cam, storage="f32"):
+    pr = qr.project(_t(sc.means), _t(sc.scales), _t(sc.quats), _t(sc.opacity), cam)
+    bins = qr.bin_sort(pr, cam.width, cam.height)
+    f32 = _t(sc.features)
+    feats, scale = (f32, None) if storage == "f32" else qr.quantize(f32, storage)
+    torch.cuda.synchronize()
+    P = int(bins.total_pairs.item())
+    host = dict(pr=dict(means2d=pr.means2d.cpu().numpy(), conic_opacity=pr.conic_opacity.cpu().numpy()),
+                gids=bins.sorted_gid.cpu().numpy()[:P].astype(np.int64),
+                offs=bins.tile_offsets.cpu().numpy().astype(np.int64))
+    if storage == "f32":
+        dec = sc.features.astype(np.float64)
+    elif storage == "bf16":
+        dec = oracle.quant.bf16_decode(feats.view(torch.int16).cpu().numpy().view(np.uint16))
+    else:
+        dec = oracle.quant.e4m3_dequantize(feats.cpu().numpy(), scale.cpu().numpy())
+    return pr, bins, feats, scale, host, dec
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _compare(gpu, orc, n_active_min=10):
+    stats = {}
+    for name, gk, ok, sl in (("features", "gf", "features", None),
+                             ("means2d", "gm", "means2d", None),
+                             ("conic", "gc", "conic", slice(0, 3)),
+                             ("opacity", "gc", "opacity", 3)):
+        g = gpu[gk] if sl is None else gpu[gk][:, sl]
+        o = orc[ok]
+        stats[name] = _rel(g, o)
+    print("gradient rel L2 errors", stats)
+    for k, v in stats.items():
+        assert v <= GRAD_TOL, (k, stats)
+    assert np.count_nonzero(np.abs(orc["opacity"]) > 0) >= n_active_min
+    return stats
+
+
+def _run(qr, sc, cam, K, storage="f32", seed=0):
+    W, H = cam.width, cam.height
+    pr, bins, feats, scale, host, dec = _setup(qr, sc, cam, storage)
+    proj = proj_for_oracle(host["pr"])
+    rng = np.random.default_rng(seed)
+    gout = rng.standard_normal((H, W, sc.dim))
+    results = {}
+    for kind in ("quantile", "dense"):
+        if kind == "quantile":
+            fw = oracle.render_quantile(proj, host["gids"], host["offs"], dec, W, H, K)
+        else:
+            fw = oracle.render_dense(proj, host["gids"], host["offs"], dec, W, H)
+        g = gout * (fw["margin"] > DECISION_WINDOW)[..., None]
+        n = sc.n
+        gf = torch.zeros(n, sc.dim, device="cuda")
+        gm = torch.zeros(n, 2, device="cuda")
+        gc = torch.zeros(n, 4, device="cuda")
+        g_t = _t(g.astype(np.float32))
+        if kind == "quantile":
+            qr._lib.qr_render_quantile_backward(W, H, qr.RenderParams().c(), K, bins.tile_offsets,
+                                                bins.sorted_gid, pr.means2d, pr.conic_opacity, feats,
+                                                scale, g_t, gf, gm, gc)
+            orc = oracle.quantile_backward(proj, host["gids"], host["offs"], dec, W, H, K, g)
+        else:
+            out = qr.render_dense(pr, bins, feats, W, H, feature_scale=scale)["out"]
+            qr._lib.qr_render_dense_backward(W, H, qr.RenderParams().c(), bins.tile_offsets,
+                                             bins.sorted_gid, pr.means2d, pr.conic_opacity, feats,
+                                             scale, out, g_t, gf, gm, gc)
+            orc = oracle.dense_backward(proj, host["gids"], host["offs"], dec, W, H, g)
+        torch.cuda.synchronize()
+        gpu = dict(gf=gf.cpu().numpy(), gm=gm.cpu().numpy(), gc=gc.cpu().numpy())
+        results[kind] = _compare(gpu, orc)
+    return results
+
+
+def test_backward_fd_subcase(qr):
+    """2,000 Gaussians, 32x32, 512-D float32 features, K = 8."""
+    sc, cam = synth.make_fd_case(seed=5)
+    _run(qr, sc, cam, 8)
+
+
+@pytest.mark.parametrize("K", [1, 4, 16, 32])
+def test_backward_ragged_small_dim(qr, K):
+    sc = synth.make_tiny(3, n=1500, dim=16)
+    cam = synth.tiny_camera(48)
+    cam.height, cam.cy = 40, 20.0
+    _run(qr, sc, cam, K, seed=K)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp8"])
+def test_backward_reduced_precision_storage(qr, storage):
+    sc, cam = synth.make_fd_case(seed=6, n=1500)
+    _run(qr, sc, cam, 8, storage=storage)
+
+
+def test_autograd_function_cosine_loss(qr):
+    """QuantileRenderFn / DenseRenderFn: loss = mean over rendered pixels of
+    1 - cos(f, t) against a seeded random target; gradients reach means2d,
+    conic_opacity and features and match the oracle given torch's dL/d(out)."""
+    sc, cam = synth.make_fd_case(seed=7, n=1200, dim=64)
+    W, H, K = cam.width, cam.height, 8
+    pr, bins, feats, scale, host, dec = _setup(qr, sc, cam)
+    proj = proj_for_oracle(host["pr"])
+    target = _t(np.random.default_rng(4).standard_normal((H, W, sc.dim)).astype(np.float32))
+    prm = qr.RenderParams()
+    for kind in ("quantile", "dense"):
+        m2 = pr.means2d.clone().requires_grad_(True)
+        co = pr.conic_opacity.clone().requires_grad_(True)
+        f = feats.clone().requires_grad_(True)
+        if kind == "quantile":
+            out, _, n_sel = qr.QuantileRenderFn.apply(m2, co, f, bins, W, H, K, prm)
+            fw = oracle.render_quantile(proj, host["gids"], host["offs"], dec, W, H, K)
+            mask = (n_sel > 0) & _t(fw["margin"] > DECISION_WINDOW)
+        else:
+            out, _, _ = qr.DenseRenderFn.apply(m2, co, f, bins, W, H, prm)
+            fw = oracle.render_dense(proj, host["gids"], host["offs"], dec, W, H)
+            mask = _t(fw["margin"] > DECISION_WINDOW) & (out.norm(dim=-1) > 1e-6)
+        cos = torch.nn.functional.cosine_similarity(out, target, dim=-1)
+        loss = ((1 - cos) * mask).sum() / mask.sum()
+        loss.backward()
+        # oracle gradients for the same dL/d(out)
+        out_d = out.detach().requires_grad_(True)
+        cos2 = torch.nn.functional.cosine_similarity(out_d, target, dim=-1)
+        (((1 - cos2) * mask).sum() / mask.sum()).backward()
+        g = out_d.grad.double().cpu().numpy()
+        if kind == "quantile":
+            orc = oracle.quantile_backward(proj, host["gids"], host["offs"], dec, W, H, K, g)
+        else:
+            orc = oracle.dense_backward(proj, host["gids"], host["offs"], dec, W, H, g)
+        gpu = dict(gf=f.grad.cpu().numpy(), gm=m2.grad.cpu().numpy(), gc=co.grad.cpu().numpy())
+        _compare(gpu, orc)

@@ -151,6 +151,30 @@ def test_bin_sort_bit_exact(qr, case):
     np.testing.assert_array_equal(res["keys"], want_keys)
 
 
+def test_bin_sort_long_tile_lists(qr):
+    """6,000 large Gaussians over a 64x64 image put ~6,000 entries in every
+    tile list: longer than a tile's LDS sort holds, so the per-tile radix sort
+    through global scratch is exercised. Ties in depth are forced."""
+    rng = np.random.default_rng(8)
+    n = 6000
+    means = np.zeros((n, 3), np.float32)
+    means[:, :2] = rng.uniform(-0.2, 0.2, (n, 2))
+    means[:, 2] = rng.integers(0, 50, n) * np.float32(0.01)  # repeated depths
+    sc = synth.Scene(means, np.full((n, 3), 0.6, np.float32), np.tile(np.float32([1, 0, 0, 0]), (n, 1)),
+                     np.full(n, 0.5, np.float32), rng.standard_normal((n, 16)).astype(np.float32))
+    cam = synth.tiny_camera()
+    res = gpu_pipeline(qr, sc, cam, 8, dense=True, debug=True)
+    g = res["pr"]
+    gids, offs, triples = oracle.bin_sort(g["rect"], g["depth"], 4, 4)
+    assert np.diff(offs).max() > 4096
+    np.testing.assert_array_equal(res["gids"], gids)
+    np.testing.assert_array_equal(res["offs"], offs)
+    want_keys = np.array([depth_bits_key(t, np.float32(d)) for t, d, _ in triples], dtype=np.uint64)
+    np.testing.assert_array_equal(res["keys"], want_keys)
+    ors = oracle_renders(res, sc.features.astype(np.float64), 64, 64, 8, tiles=[0, 5, 15])
+    check_all(res, ors, 64, 64, tiles=[0, 5, 15])
+
+
 def test_render_parity_tiny(qr):
     sc, cam = synth.make_tiny(0), synth.tiny_camera()
     res = gpu_pipeline(qr, sc, cam, 8)
