@@ -42,16 +42,26 @@ def parse():
                     help="seconds of FP64 CPU reference work (0 disables)")
     ap.add_argument("--renders-only", action="store_true",
                     help="profiling aid: skip the CPU reference")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="profiling aid: first run a plain 1 GiB device copy, whose known "
+                         "traffic calibrates the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--workload", default="room", choices=["room", "precision", "diff", "batched"],
+                    help="room (default, the headline metric); precision: 1M Gaussians at "
+                         "1296x968 with bf16 features, K in {4,8,16}; diff: 500k Gaussians, bf16, "
+                         "forward+backward through autograd; batched: 32 views of 4 scenes "
+                         "(0.3M-3M Gaussians) at 1280x720, fp8 e4m3 features, one persistent launch")
     return ap.parse_args()
 
 
 class FrameRunner:
     """Preallocated buffers and the per-frame launch sequence."""
 
-    def __init__(self, qr, L, scene_t, cams, K, capacity, dim):
+    def __init__(self, qr, L, scene_t, cams, K, capacity, dim, feats=None, scale=None):
         import torch
         self.qr, self.L, self.K = qr, L, K
         self.s = scene_t
+        self.feats = scene_t["feats"] if feats is None else feats
+        self.scale = scale
         self.cams = [L.make_camera(c) for c in cams]
         self.W, self.H = cams[0].width, cams[0].height
         n = scene_t["means"].shape[0]
@@ -71,12 +81,12 @@ class FrameRunner:
 
     def render_q(self, bins):
         self.L.qr_render_quantile(self.W, self.H, self.prm, self.K, bins.tile_offsets, bins.sorted_gid,
-                                  self.pr.means2d, self.pr.conic_opacity, self.s["feats"], None,
+                                  self.pr.means2d, self.pr.conic_opacity, self.feats, self.scale,
                                   self.out, self.aux_f, self.aux_i)
 
     def render_d(self, bins):
         self.L.qr_render_dense(self.W, self.H, self.prm, bins.tile_offsets, bins.sorted_gid,
-                               self.pr.means2d, self.pr.conic_opacity, self.s["feats"], None,
+                               self.pr.means2d, self.pr.conic_opacity, self.feats, self.scale,
                                self.out, self.aux_f, self.aux_i)
 
 
@@ -155,7 +165,30 @@ def main():
         print("bench.py measures one GPU only: the renderer needs no exchange between GPUs "
               "and this build runs on a single MI355X; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    {"room": run_room, "precision": run_precision, "diff": run_diff,
+     "batched": run_batched}[args.workload](args)
+
+
+def _base_record(args, value, unit, dtype, workload, ms_per_step):
+    return {"metric": METRIC, "value": round(value, 2), "unit": unit, "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": {"workload": workload}}
+
+
+def _scene_tensors(sc, torch):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return dict(means=t(sc.means), scales=t(sc.scales), quats=t(sc.quats), opacity=t(sc.opacity))
+
+
+def run_room(args):
     import torch
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     import paper_2512_20927_amd as qr
     from paper_2512_20927_amd import _lib as L
     import synth
@@ -239,6 +272,209 @@ def main():
         "cpu_baseline": cpu,
         "setup_s": round(t_setup, 1),
     }
+    print(json.dumps(rec))
+
+
+def run_precision(args):
+    """1M Gaussians, 1296x968, 512-D bf16 features: Q-Render K in {4, 8, 16}
+    and the dense blend, 4 views."""
+    import torch
+    import paper_2512_20927_amd as qr
+    from paper_2512_20927_amd import _lib as L
+    import synth
+    cfg = synth.CONFIGS["precision"]
+    sc = synth.make_room(cfg["n"], cfg["seed"], dim=cfg["dim"])
+    cams = synth.room_poses(cfg["pose_seeds"], cfg["width"], cfg["height"], cfg["fx"])
+    s = _scene_tensors(sc, torch)
+    f32 = torch.from_numpy(sc.features).cuda()
+    feats, _ = qr.quantize(f32, "bf16")
+    del f32
+    s["feats"] = feats
+    pairs = []
+    for c in cams:
+        pr = qr.project(s["means"], s["scales"], s["quats"], s["opacity"], c)
+        pairs.append(qr.count_pairs(pr))
+    cap = int(max(pairs) * 1.05) + 1024
+    per_k, render_ms = {}, {}
+    for K in cfg["Ks"]:
+        runner = FrameRunner(qr, L, s, cams, K, cap, cfg["dim"], feats=feats)
+        dt, kms = timed(runner, "q", args.steps, args.warmup, len(cams))
+        per_k[str(K)] = round(args.steps * len(cams) / dt, 2)
+        render_ms[str(K)] = round(kms, 4)
+    dt_d, kms_d = timed(runner, "d", args.steps, args.warmup, len(cams))
+    d_fps = args.steps * len(cams) / dt_d
+    rec = _base_record(args, per_k["8"], "frames/s", "bf16",
+                       "precision: 1M Gaussians, 1296x968, fx=fy=1168.4, 512-D bf16 features "
+                       "(float32 accumulation), 4 poses per step; value = Q-Render K=8",
+                       1e3 * args.steps * len(cams) / per_k["8"] / args.steps)
+    rec.update({"q_fps_per_K": per_k, "dense_value": round(d_fps, 2),
+                "q_over_dense": round(per_k["8"] / d_fps, 3),
+                "render_ms": {"quantile_per_K": render_ms, "dense": round(kms_d, 4)},
+                "workload_stats": {"pairs_mean": float(np.mean(pairs))}})
+    print(json.dumps(rec))
+
+
+def run_diff(args):
+    """500k Gaussians, 640x480, 512-D bf16 features: Q-Render K=8 forward +
+    backward through QuantileRenderFn with a cosine-distance loss."""
+    import torch
+    import paper_2512_20927_amd as qr
+    import synth
+    cfg = synth.CONFIGS["diff"]
+    sc = synth.make_room(cfg["n"], cfg["seed"], dim=cfg["dim"])
+    cam = synth.room_poses(cfg["pose_seeds"], cfg["width"], cfg["height"], cfg["fx"])[0]
+    s = _scene_tensors(sc, torch)
+    master = torch.from_numpy(sc.features).cuda().requires_grad_(True)
+    storage = qr.quantize(master.detach(), "bf16")
+    W, H, K = cfg["width"], cfg["height"], cfg["K"]
+    target = torch.from_numpy(np.random.default_rng(cfg["target_seed"]).standard_normal(
+        (H, W, cfg["dim"]), dtype=np.float32)).cuda()
+    prm = qr.RenderParams()
+    pr = qr.project(s["means"], s["scales"], s["quats"], s["opacity"], cam)
+    binner = qr.Binner(sc.n, W, H, int(qr.count_pairs(pr) * 1.05) + 1024)
+    m2 = pr.means2d.detach().clone().requires_grad_(True)
+    co = pr.conic_opacity.detach().clone().requires_grad_(True)
+
+    def step(which):
+        qr.project(s["means"], s["scales"], s["quats"], s["opacity"], cam, out=pr)
+        bins = binner(pr)
+        with torch.no_grad():
+            m2.copy_(pr.means2d)
+            co.copy_(pr.conic_opacity)
+        if which == "q":
+            out, _, n_sel = qr.QuantileRenderFn.apply(m2, co, master, bins, W, H, K, prm, (storage[0], None))
+            mask = n_sel > 0
+        else:
+            out, _, _ = qr.DenseRenderFn.apply(m2, co, master, bins, W, H, prm, (storage[0], None))
+            mask = torch.ones(H, W, dtype=torch.bool, device="cuda")
+        cos = torch.nn.functional.cosine_similarity(out, target, dim=-1)
+        loss = ((1 - cos) * mask).sum() / mask.sum().clamp(min=1)
+        master.grad = m2.grad = co.grad = None
+        loss.backward()
+
+    res = {}
+    for which in ("q", "d"):
+        for _ in range(args.warmup):
+            step(which)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(which)
+        torch.cuda.synchronize()
+        res[which] = args.steps / (time.perf_counter() - t0)
+    rec = _base_record(args, res["q"], "iterations/s", "bf16",
+                       "diff: 500k Gaussians, 640x480, 512-D bf16 features, Q-Render K=8 forward + "
+                       "backward (autograd, cosine loss); one iteration = one view",
+                       1e3 / res["q"])
+    rec.update({"dense_value": round(res["d"], 2), "q_over_dense": round(res["q"] / res["d"], 3)})
+    print(json.dumps(rec))
+
+
+def run_batched(args):
+    """32 views over 4 scenes (0.3M, 0.8M, 1.5M, 3M Gaussians) at 1280x720,
+    512-D fp8 e4m3 features with per-Gaussian scales: per batch, every view
+    is projected and binned, a device-built schedule orders the (view, tile)
+    items and one persistent launch renders all of them (K=8); the
+    autotuner's choice of schedule and workgroups is used. Then the
+    Q-Render backward of every view."""
+    import torch
+    import paper_2512_20927_amd as qr
+    from paper_2512_20927_amd import _lib as L
+    from paper_2512_20927_amd.batched import BatchedQuantile, autotune
+    import synth
+    K, D, W, H = 8, 512, 1280, 720
+    sizes, seeds, per = (300_000, 800_000, 1_500_000, 3_000_000), (10, 11, 12, 13), 8
+    scenes = []
+    for n, sd in zip(sizes, seeds):
+        sc = synth.make_room(n, sd, dim=D)
+        st = _scene_tensors(sc, torch)
+        f32 = torch.from_numpy(sc.features).cuda()
+        st["codes"], st["scale"] = qr.quantize(f32, "fp8")
+        del f32, sc
+        scenes.append(st)
+    prm = qr.RenderParams()
+    cams, scene_of = [], []
+    seed = 300
+    for si in range(len(sizes)):
+        for _ in range(per):
+            cams.append(synth.room_camera(seed, W, H, 1154.0))
+            scene_of.append(si)
+            seed += 1
+    n_views = len(cams)
+    prs, binners, views = [], [], []
+    ws = None
+    for c, si in zip(cams, scene_of):
+        st = scenes[si]
+        pr = qr.project(st["means"], st["scales"], st["quats"], st["opacity"], c)
+        cap = int(qr.count_pairs(pr) * 1.05) + 1024
+        b = qr.Binner(st["means"].shape[0], W, H, cap)
+        if ws is None or ws.numel() < b.workspace.numel():
+            ws = b.workspace
+        b.workspace = None
+        prs.append(pr)
+        binners.append(b)
+    for b in binners:  # one shared binning workspace (views are binned in turn)
+        b.workspace = ws
+    outs = [torch.empty(H, W, D, device="cuda") for _ in range(n_views)]
+    for v in range(n_views):
+        st = scenes[scene_of[v]]
+        bins = binners[v].bins
+        views.append(dict(tile_offsets=bins.tile_offsets, sorted_gid=bins.sorted_gid,
+                          means2d=prs[v].means2d, conic_opacity=prs[v].conic_opacity,
+                          features=st["codes"], feature_scale=st["scale"], out=outs[v],
+                          T_q=None, n_sel=None, width=W, height=H))
+    cam_c = [L.make_camera(c) for c in cams]
+    prm_c = prm.c()
+
+    def front():
+        for v in range(n_views):
+            st = scenes[scene_of[v]]
+            pr = prs[v]
+            L.qr_project(st["means"], st["scales"], st["quats"], st["opacity"], cam_c[v], prm_c,
+                         pr.means2d, pr.conic_opacity, pr.depth, pr.tile_rect, pr.tiles_touched)
+            binners[v](pr)
+
+    front()
+    bq = BatchedQuantile(views, K, D, L.QR_FP8_E4M3, prm_c)
+    tuned, timings = autotune(bq, use_cache=False)
+    for _ in range(args.warmup):
+        front()
+        bq.render(tuned["schedule"], tuned["wg_per_cu"])
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        front()
+        ev[2 * i].record()
+        bq.render(tuned["schedule"], tuned["wg_per_cu"])
+        ev[2 * i + 1].record()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    render_ms = float(np.mean([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(args.steps)]))
+    # backward of every view (non-batched kernel), one grad_out buffer reused
+    gout = torch.randn(H, W, D, device="cuda")
+    gfs = [torch.zeros(st["means"].shape[0], D, device="cuda") for st in scenes]
+    gms = [torch.zeros(st["means"].shape[0], 2, device="cuda") for st in scenes]
+    gcs = [torch.zeros(st["means"].shape[0], 4, device="cuda") for st in scenes]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for v in range(n_views):
+        si = scene_of[v]
+        st = scenes[si]
+        b = binners[v].bins
+        L.qr_render_quantile_backward(W, H, prm_c, K, b.tile_offsets, b.sorted_gid, prs[v].means2d,
+                                      prs[v].conic_opacity, st["codes"], st["scale"], gout,
+                                      gfs[si], gms[si], gcs[si])
+    torch.cuda.synchronize()
+    bwd_s = time.perf_counter() - t1
+    rec = _base_record(args, n_views * args.steps / dt, "views/s", "fp8",
+                       "batched: 32 views over 4 room scenes (0.3M/0.8M/1.5M/3M Gaussians), "
+                       "1280x720, fx=fy=1154, 512-D fp8 e4m3 features with per-Gaussian scale, "
+                       "Q-Render K=8, one persistent launch per batch",
+                       dt / args.steps * 1e3)
+    rec.update({"render_ms_per_batch": round(render_ms, 3), "autotuned": tuned,
+                "autotune_ms": {k: round(v, 3) for k, v in timings.items()},
+                "backward_views_per_s": round(n_views / bwd_s, 2)})
     print(json.dumps(rec))
 
 

@@ -46,6 +46,7 @@ extern "C" {
 #define QR_TILE 16
 #define QR_MAX_K 32        /* largest number of quantile Gaussians per ray */
 #define QR_MAX_DIM 4096    /* largest feature width D */
+#define QR_BATCH_TILE_BITS 20  /* batched schedule item = (view << 20) | tile */
 
 typedef enum qr_status {
   QR_OK = 0,
@@ -91,6 +92,23 @@ typedef struct qr_params {
   float dilation;
   float guard;
 } qr_params;
+
+/* One view of a batched render (qr_render_quantile_batched). All pointers are
+ * device pointers with the meaning of the same-named qr_render_quantile
+ * arguments; T_q and n_sel may be NULL. Views may belong to different scenes
+ * (different Gaussian sets and feature tables) and have different sizes. */
+typedef struct qr_view {
+  const uint32_t* tile_offsets;
+  const uint32_t* sorted_gid;
+  const float* means2d;
+  const float* conic_opacity;
+  const void* features;
+  const float* feature_scale;
+  float* out;
+  float* T_q;
+  int32_t* n_sel;
+  int32_t width, height;
+} qr_view;
 
 /* Library version string (static storage). */
 const char* qr_version(void);
@@ -203,6 +221,39 @@ int qr_render_quantile(void* stream, int32_t width, int32_t height,
                        const float* feature_scale, int32_t dim,
                        float* out, float* T_q, int32_t* n_sel,
                        int32_t* sel_gid, float* sel_w);
+
+/*
+ * qr_render_quantile_batched - Quantile Rendering of many views in one
+ * persistent launch: `n_workgroups` workgroups take (view, tile) work items
+ * from `schedule` (device u32[n_items], item = (view << QR_BATCH_TILE_BITS) |
+ * tile, views < 4096, tiles per view < 2^20) in order through an atomic
+ * counter, each rendering one 16x16 tile of one view exactly as
+ * qr_render_quantile does. The schedule decides load balance (e.g. the
+ * longest tile lists first); every (view, tile) to be rendered must appear
+ * once. `views` is a DEVICE array of n_views qr_view records. All views share
+ * K, the feature dtype and dim. `workspace` (device, >= 4 bytes) holds the
+ * work counter; it is reset by the call.
+ */
+int qr_render_quantile_batched(void* stream, int32_t n_views, const qr_view* views,
+                               const qr_params* prm, int32_t K, int32_t dtype,
+                               int32_t dim, const uint32_t* schedule,
+                               int64_t n_items, int32_t n_workgroups,
+                               void* workspace, size_t workspace_bytes);
+
+/*
+ * qr_batch_schedule - builds a schedule for qr_render_quantile_batched on the
+ * device, without a host round trip: every (view, tile) item, ordered by the
+ * length of its tile list, longest first, in power-of-two length classes
+ * (order inside a class is unspecified). `view_first` (device i32[n_views+1])
+ * holds each view's first item index (prefix sums of its tile counts), so
+ * item i belongs to the view v with view_first[v] <= i < view_first[v+1] and
+ * is its tile i - view_first[v]. `views` is the device qr_view array whose
+ * tile_offsets have been filled by qr_bin_sort. Writes schedule u32[n_items].
+ * `workspace`: device, >= 256 bytes.
+ */
+int qr_batch_schedule(void* stream, int32_t n_views, const qr_view* views,
+                      const int32_t* view_first, int64_t n_items, uint32_t* schedule,
+                      void* workspace, size_t workspace_bytes);
 
 /*
  * qr_render_dense_backward / qr_render_quantile_backward - gradients of the

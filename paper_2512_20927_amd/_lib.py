@@ -25,7 +25,9 @@ EXPORTED = [
     "qr_version", "qr_last_error", "qr_project", "qr_count_pairs",
     "qr_bin_sort_workspace_size", "qr_bin_sort", "qr_render_dense", "qr_render_quantile",
     "qr_render_dense_backward", "qr_render_quantile_backward", "qr_quantize_features",
+    "qr_render_quantile_batched", "qr_batch_schedule",
 ]
+QR_BATCH_TILE_BITS = 20
 
 
 class QRError(RuntimeError):
@@ -42,6 +44,14 @@ class qr_camera(ctypes.Structure):
                 ("z_near", ctypes.c_float)]
 
 
+class qr_view(ctypes.Structure):
+    _fields_ = [("tile_offsets", ctypes.c_void_p), ("sorted_gid", ctypes.c_void_p),
+                ("means2d", ctypes.c_void_p), ("conic_opacity", ctypes.c_void_p),
+                ("features", ctypes.c_void_p), ("feature_scale", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("T_q", ctypes.c_void_p), ("n_sel", ctypes.c_void_p),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
 class qr_params(ctypes.Structure):
     _fields_ = [("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("T_eps", ctypes.c_float), ("dilation", ctypes.c_float),
@@ -50,7 +60,7 @@ class qr_params(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libqrender.so is not built; run `python -m paper_2512_20927_amd.build` "
+        raise ImportError("libqrender.so is not built; run `python paper_2512_20927_amd/build.py` "
                           "(expected at %s)" % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
@@ -68,6 +78,8 @@ def _load():
         "qr_render_dense_backward": ([P, i32, i32, prm_p, P, P, P, P, P, i32, P, i32, P, P, P, P, P], i32),
         "qr_render_quantile_backward": ([P, i32, i32, prm_p, i32, P, P, P, P, P, i32, P, i32, P, P, P, P], i32),
         "qr_quantize_features": ([P, i64, i32, P, i32, P, P], i32),
+        "qr_render_quantile_batched": ([P, i32, P, prm_p, i32, i32, i32, P, i64, i32, P, sz], i32),
+        "qr_batch_schedule": ([P, i32, P, P, i64, P, P, sz], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -307,3 +319,39 @@ def qr_quantize_features(features, dtype_code, out, scale=None, stream=None):
         _need(scale, n, F32, "scale")
     _check(_LIB.qr_quantize_features(_stream(stream), features.shape[0], features.shape[1],
                                      _ptr(features), dtype_code, _ptr(out), _ptr(scale)))
+
+
+def qr_render_quantile_batched(n_views, views_dev, params, K, dtype_code, dim, schedule, n_workgroups,
+                               workspace, stream=None):
+    """views_dev: uint8 device tensor holding n_views qr_view records (see
+    pack_views); schedule: int32 device tensor of packed (view, tile) items."""
+    if views_dev.numel() < n_views * ctypes.sizeof(qr_view):
+        raise ValueError("views_dev is smaller than n_views qr_view records")
+    _need(schedule, 0, I32, "schedule")
+    _check(_LIB.qr_render_quantile_batched(_stream(stream), n_views, _ptr(views_dev),
+                                           ctypes.byref(params), K, dtype_code, dim,
+                                           _ptr(schedule), schedule.numel(), n_workgroups,
+                                           _ptr(workspace), workspace.numel() * workspace.element_size()))
+
+
+def pack_views(views) -> bytes:
+    """Host bytes of a qr_view array; `views` are dicts of tensors / ints."""
+    arr = (qr_view * len(views))()
+    for i, v in enumerate(views):
+        for f in ("tile_offsets", "sorted_gid", "means2d", "conic_opacity", "features", "out"):
+            setattr(arr[i], f, v[f].data_ptr())
+        for f in ("feature_scale", "T_q", "n_sel"):
+            t = v.get(f)
+            setattr(arr[i], f, t.data_ptr() if t is not None else None)
+        arr[i].width, arr[i].height = int(v["width"]), int(v["height"])
+    return bytes(arr)
+
+
+def qr_batch_schedule(n_views, views_dev, view_first, schedule, workspace, stream=None):
+    if views_dev.numel() < n_views * ctypes.sizeof(qr_view):
+        raise ValueError("views_dev is smaller than n_views qr_view records")
+    _need(view_first, n_views + 1, I32, "view_first")
+    _need(schedule, 0, I32, "schedule")
+    _check(_LIB.qr_batch_schedule(_stream(stream), n_views, _ptr(views_dev), _ptr(view_first),
+                                  schedule.numel(), _ptr(schedule), _ptr(workspace),
+                                  workspace.numel() * workspace.element_size()))

@@ -1,0 +1,114 @@
+"""Batched multi-view Quantile Rendering in one persistent launch, and the
+autotuner that picks its tile schedule.
+
+A batch is any list of views (each with its own scene, bins and output
+buffer). ``BatchedQuantile`` packs the views' device pointers into a device
+``qr_view`` table once; ``render`` then issues a single persistent launch over
+all (view, tile) items. Two schedules are available: ``natural`` (view-major
+order, fixed) and ``heavy`` (longest tile lists first, built on the device by
+``qr_batch_schedule`` from the current bins, so no host round trip). The
+autotuner times the candidates (schedule x workgroups per CU) with HIP events
+and caches the winner as JSON keyed by device, shapes and K.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import _lib as L
+from .render import tiles_of
+
+SCHEDULES = ("natural", "heavy")
+
+
+class BatchedQuantile:
+    def __init__(self, views, K: int, dim: int, dtype_code: int, params):
+        """views: list of dicts with tile_offsets, sorted_gid, means2d,
+        conic_opacity, features, feature_scale (or None), out, T_q, n_sel (or
+        None), width, height (all tensors on one device)."""
+        self.n_views = len(views)
+        self.K, self.dim, self.dtype_code, self.params = K, dim, dtype_code, params
+        dev = views[0]["out"].device
+        self._views = views  # keeps the tensors alive
+        raw = L.pack_views(views)
+        self.views_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+        counts = [tiles_of(v["width"], v["height"])[0] * tiles_of(v["width"], v["height"])[1] for v in views]
+        first = [0]
+        for c in counts:
+            first.append(first[-1] + c)
+        self.n_items = first[-1]
+        self.view_first = torch.tensor(first, dtype=torch.int32, device=dev)
+        nat = [(v << L.QR_BATCH_TILE_BITS) | t for v, c in enumerate(counts) for t in range(c)]
+        self.natural = torch.tensor(nat, dtype=torch.int64, device=dev).to(torch.int32)
+        self.heavy = torch.empty(self.n_items, dtype=torch.int32, device=dev)
+        self.sched_ws = torch.empty(64, dtype=torch.int32, device=dev)
+        self.counter = torch.empty(1, dtype=torch.int32, device=dev)
+        props = torch.cuda.get_device_properties(dev)
+        self.n_cu = props.multi_processor_count
+        self.device_name = props.name
+
+    def schedule(self, kind: str):
+        if kind == "natural":
+            return self.natural
+        if kind == "heavy":
+            L.qr_batch_schedule(self.n_views, self.views_dev, self.view_first, self.heavy, self.sched_ws)
+            return self.heavy
+        raise ValueError(kind)
+
+    def render(self, kind: str = "heavy", wg_per_cu: int = 4):
+        sched = self.schedule(kind)
+        L.qr_render_quantile_batched(self.n_views, self.views_dev, self.params, self.K,
+                                     self.dtype_code, self.dim, sched, self.n_cu * wg_per_cu,
+                                     self.counter)
+
+    def key(self) -> str:
+        shapes = sorted({(v["width"], v["height"]) for v in self._views})
+        return "%s|views=%d|%s|D=%d|K=%d|dtype=%d" % (self.device_name, self.n_views, shapes,
+                                                      self.dim, self.K, self.dtype_code)
+
+
+def default_cache_path() -> str:
+    return os.environ.get("QRENDER_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "qrender", "autotune.json"))
+
+
+def autotune(bq: BatchedQuantile, wg_per_cu=(2, 4, 6, 8), schedules=SCHEDULES, reps: int = 3,
+             cache_path: str | None = None, use_cache: bool = True):
+    """Times every (schedule, workgroups per CU) candidate and returns
+    (best_config, timings_ms). The best is cached under bq.key()."""
+    cache_path = cache_path or default_cache_path()
+    cache = {}
+    if use_cache and os.path.exists(cache_path):
+        try:
+            with open(cache_path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+        if bq.key() in cache:
+            return cache[bq.key()], {}
+    timings = {}
+    for kind in schedules:
+        for w in wg_per_cu:
+            bq.render(kind, w)  # warm
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                bq.render(kind, w)
+            b.record()
+            torch.cuda.synchronize()
+            timings["%s/%d" % (kind, w)] = a.elapsed_time(b) / reps
+    best = min(timings, key=timings.get)
+    kind, w = best.split("/")
+    cfg = {"schedule": kind, "wg_per_cu": int(w), "ms": timings[best]}
+    cache[bq.key()] = cfg
+    try:
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    except OSError:
+        pass
+    return cfg, timings

@@ -1,6 +1,7 @@
 """Builds libqrender.so (the HIP kernels and the C ABI) in-tree for gfx950.
 
-Usage: python -m paper_2512_20927_amd.build [-v]
+Usage: python paper_2512_20927_amd/build.py [-v]   (run by path, so that the
+package, which loads the library on import, is not imported first)
 """
 
 from __future__ import annotations
@@ -26,6 +27,7 @@ SOURCES = [
     "render_dense.hip",
     "render_backward.hip",
     "quantize.hip",
+    "schedule.hip",
 ]
 
 # Packed FP32 instructions are switched off: float code is compiled to

@@ -4,7 +4,8 @@
 // the pixel; as in 3D-GS it is built per 16x16 tile. Instead of one global
 // sort of (tile, depth) keys this is a bucket sort by tile followed by an
 // independent sort of each tile's bucket in LDS:
-//   1. count: one atomic increment per (Gaussian, covered tile);
+//   1. count: exclusive scan of tiles_touched gives each Gaussian's pair
+//      range; one thread per pair then increments its tile's counter;
 //   2. exclusive scan of the counts -> tile_offsets (CSR) and the pair count;
 //   3. scatter: each pair claims a slot in its tile's bucket with an atomic
 //      cursor and stores the 64-bit key (float bits of depth << 32 | id);
@@ -106,32 +107,52 @@ zero_u32_kernel(uint32_t* __restrict__ a, int64_t n) {
   for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) a[i] = 0u;
 }
 
-__global__ void __launch_bounds__(256)
-tile_count_kernel(int64_t n, const int4* __restrict__ rect, const uint32_t* __restrict__ touched,
-                  int tiles_x, uint32_t* __restrict__ cnt) {
-  const int64_t i = blockIdx.x * 256LL + threadIdx.x;
-  if (i >= n || touched[i] == 0) return;
-  const int4 r = rect[i];
-  for (int ty = r.y; ty < r.w; ++ty)
-    for (int tx = r.x; tx < r.z; ++tx) atomicAdd(&cnt[ty * tiles_x + tx], 1u);
+// One thread per (Gaussian, tile) pair: the pair's Gaussian is found by
+// binary search in the exclusive scan of tiles_touched (pair_off[0..n]), so a
+// Gaussian that covers a thousand tiles costs a thousand threads rather than a
+// thousand serial iterations of one thread. Grid-stride over the pair count
+// read from device memory.
+__device__ __forceinline__ void pair_tile(int64_t k, int64_t n, const uint32_t* __restrict__ pair_off,
+                                          const int4* __restrict__ rect, int tiles_x, int64_t* gid,
+                                          int* tile) {
+  int64_t lo = 0, hi = n;  // find the last i with pair_off[i] <= k
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (pair_off[mid] <= static_cast<uint32_t>(k)) lo = mid; else hi = mid;
+  }
+  const int4 r = rect[lo];
+  const int w = r.z - r.x;
+  const int l = static_cast<int>(k - pair_off[lo]);
+  *gid = lo;
+  *tile = (r.y + l / w) * tiles_x + r.x + l % w;
 }
 
 __global__ void __launch_bounds__(256)
-tile_scatter_kernel(int64_t n, const int4* __restrict__ rect, const uint32_t* __restrict__ touched,
+tile_count_kernel(int64_t n, const uint32_t* __restrict__ pair_off, const int4* __restrict__ rect,
+                  int tiles_x, uint32_t* __restrict__ cnt) {
+  const int64_t P = pair_off[n];
+  for (int64_t k = blockIdx.x * 256LL + threadIdx.x; k < P; k += 256LL * gridDim.x) {
+    int64_t g;
+    int t;
+    pair_tile(k, n, pair_off, rect, tiles_x, &g, &t);
+    atomicAdd(&cnt[t], 1u);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+tile_scatter_kernel(int64_t n, const uint32_t* __restrict__ pair_off, const int4* __restrict__ rect,
                     const float* __restrict__ depth, int tiles_x,
                     const uint32_t* __restrict__ offsets, uint32_t* __restrict__ cursor,
                     int64_t capacity, unsigned long long* __restrict__ bucket) {
-  const int64_t i = blockIdx.x * 256LL + threadIdx.x;
-  if (i >= n || touched[i] == 0) return;
-  const int4 r = rect[i];
-  const unsigned long long key =
-      (static_cast<unsigned long long>(__float_as_uint(depth[i])) << 32) | static_cast<uint32_t>(i);
-  for (int ty = r.y; ty < r.w; ++ty) {
-    for (int tx = r.x; tx < r.z; ++tx) {
-      const int t = ty * tiles_x + tx;
-      const int64_t slot = static_cast<int64_t>(offsets[t]) + atomicAdd(&cursor[t], 1u);
-      if (slot < capacity) bucket[slot] = key;
-    }
+  const int64_t P = pair_off[n];
+  for (int64_t k = blockIdx.x * 256LL + threadIdx.x; k < P; k += 256LL * gridDim.x) {
+    int64_t g;
+    int t;
+    pair_tile(k, n, pair_off, rect, tiles_x, &g, &t);
+    const int64_t slot = static_cast<int64_t>(offsets[t]) + atomicAdd(&cursor[t], 1u);
+    if (slot < capacity)
+      bucket[slot] = (static_cast<unsigned long long>(__float_as_uint(depth[g])) << 32) |
+                     static_cast<uint32_t>(g);
   }
 }
 
@@ -248,14 +269,16 @@ tile_sort_kernel(int n_tiles, const uint32_t* __restrict__ offsets, int64_t capa
 
 // ---- workspace layout --------------------------------------------------------
 struct Layout {
-  size_t cnt, cursor, part, bucket, scratch, bytes;
+  size_t pair_off, part_n, cnt, cursor, part, bucket, scratch, bytes;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-static Layout layout(int64_t n_tiles, int64_t capacity) {
+static Layout layout(int64_t n, int64_t n_tiles, int64_t capacity) {
   Layout L{};
   size_t o = 0;
+  L.pair_off = o; o = align256(o + sizeof(uint32_t) * (n + 1));
+  L.part_n = o;   o = align256(o + sizeof(uint32_t) * (scan_parts(n) + 1));
   L.cnt = o;     o = align256(o + sizeof(uint32_t) * (n_tiles + 1));
   L.cursor = o;  o = align256(o + sizeof(uint32_t) * (n_tiles + 1));
   L.part = o;    o = align256(o + sizeof(uint32_t) * (scan_parts(n_tiles) + 1));
@@ -280,7 +303,7 @@ extern "C" int qr_bin_sort_workspace_size(int64_t n, int32_t tiles_x, int32_t ti
   if (!bytes) return fail(QR_ERR_INVALID_ARG, "qr_bin_sort_workspace_size: null result pointer");
   if (n < 0 || capacity < 0 || tiles_x <= 0 || tiles_y <= 0)
     return fail(QR_ERR_INVALID_ARG, "qr_bin_sort_workspace_size: bad sizes");
-  *bytes = layout(static_cast<int64_t>(tiles_x) * tiles_y, capacity).bytes;
+  *bytes = layout(n, static_cast<int64_t>(tiles_x) * tiles_y, capacity).bytes;
   return QR_OK;
 }
 
@@ -300,13 +323,15 @@ extern "C" int qr_bin_sort(void* stream, int64_t n, int32_t tiles_x, int32_t til
   if (n > 0 && (!tile_rect || !tiles_touched || !depth))
     return fail(QR_ERR_INVALID_ARG, "qr_bin_sort: null input pointer");
   if (capacity > 0 && !sorted_gid) return fail(QR_ERR_INVALID_ARG, "qr_bin_sort: null sorted_gid");
-  const Layout L = layout(n_tiles, capacity);
+  const Layout L = layout(n, n_tiles, capacity);
   if (workspace_bytes < L.bytes)
     return fail(QR_ERR_CAPACITY, "qr_bin_sort: workspace needs %zu bytes, got %zu", L.bytes,
                 workspace_bytes);
 
   hipStream_t s = as_stream(stream);
   char* ws = static_cast<char*>(workspace);
+  auto* pair_off = reinterpret_cast<uint32_t*>(ws + L.pair_off);
+  auto* part_n = reinterpret_cast<uint32_t*>(ws + L.part_n);
   auto* cnt = reinterpret_cast<uint32_t*>(ws + L.cnt);
   auto* cursor = reinterpret_cast<uint32_t*>(ws + L.cursor);
   auto* part = reinterpret_cast<uint32_t*>(ws + L.part);
@@ -314,18 +339,25 @@ extern "C" int qr_bin_sort(void* stream, int64_t n, int32_t tiles_x, int32_t til
   auto* scratch = reinterpret_cast<unsigned long long*>(ws + L.scratch);
 
   // counters and cursors are adjacent in the layout: one fill clears both
-  const int64_t zero_n = static_cast<int64_t>((L.bucket - L.cnt) / sizeof(uint32_t));
+  const int64_t zero_n = static_cast<int64_t>((L.part - L.cnt) / sizeof(uint32_t));
   hipLaunchKernelGGL(zero_u32_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(ceil_div(zero_n, 256), 1024))),
                      dim3(256), 0, s, cnt, zero_n);
-  const unsigned gblocks = static_cast<unsigned>(std::max<int64_t>(ceil_div(n, 256), 1));
-  if (n > 0)
-    hipLaunchKernelGGL(tile_count_kernel, dim3(gblocks), dim3(256), 0, s, n,
-                       reinterpret_cast<const int4*>(tile_rect), tiles_touched, tiles_x, cnt);
-  scan_exclusive(cnt, tile_offsets, n_tiles, part, total_pairs, s);
-  if (n > 0 && capacity > 0)
-    hipLaunchKernelGGL(tile_scatter_kernel, dim3(gblocks), dim3(256), 0, s, n,
-                       reinterpret_cast<const int4*>(tile_rect), tiles_touched, depth, tiles_x,
-                       tile_offsets, cursor, capacity, bucket);
+  // pairs per Gaussian -> pair offsets (pair_off[n] = pair count)
+  if (n > 0) {
+    scan_exclusive(tiles_touched, pair_off, n, part_n, nullptr, s);
+    // grid-stride kernels over the pairs; the grid is sized by the capacity
+    const unsigned pblocks = static_cast<unsigned>(
+        std::min<int64_t>(std::max<int64_t>(ceil_div(capacity, 256), 1), 8192));
+    hipLaunchKernelGGL(tile_count_kernel, dim3(pblocks), dim3(256), 0, s, n, pair_off,
+                       reinterpret_cast<const int4*>(tile_rect), tiles_x, cnt);
+    scan_exclusive(cnt, tile_offsets, n_tiles, part, total_pairs, s);
+    if (capacity > 0)
+      hipLaunchKernelGGL(tile_scatter_kernel, dim3(pblocks), dim3(256), 0, s, n, pair_off,
+                         reinterpret_cast<const int4*>(tile_rect), depth, tiles_x, tile_offsets,
+                         cursor, capacity, bucket);
+  } else {
+    scan_exclusive(cnt, tile_offsets, n_tiles, part, total_pairs, s);
+  }
   if (capacity > 0)
     hipLaunchKernelGGL(tile_sort_kernel, dim3(static_cast<unsigned>(n_tiles)), dim3(256), 0, s,
                        static_cast<int>(n_tiles), tile_offsets, capacity, bits_for(n), bucket,

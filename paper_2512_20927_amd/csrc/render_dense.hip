@@ -7,24 +7,35 @@
 // computes one tile x one 128-column slice of D:
 //   - 32 list entries at a time, each pixel thread walks its transmittance
 //     chain and writes its 32 weights into LDS; the 32 feature rows (slice)
-//     are decoded to float32 into LDS alongside;
-//   - each wave64 owns 64 pixels (4 pixel rows) x 128 columns and accumulates
-//     them with v_mfma_f32_16x16x4_f32 (A = weights, B = features, 32 fp32
-//     accumulator tiles of 16x16 per wave);
+//     are decoded to float32 alongside;
+//   - both operands are split into bfloat16 pairs x = x_hi + x_lo (x_hi the
+//     rounded value, x_lo the rounded remainder) and the product is formed as
+//     W_hi F_hi + W_hi F_lo + W_lo F_hi on v_mfma_f32_16x16x32_bf16 with
+//     float32 accumulation (bf16 features are exact in x_hi, so their F_lo
+//     term is dropped). The omitted W_lo F_lo term and the second roundings
+//     are below 2^-16 of each product, i.e. float32-class accuracy at the
+//     bf16 matrix rate;
+//   - each wave64 owns 64 pixels (4 pixel rows) x 128 columns: 32
+//     accumulator tiles of 16x16;
 //   - the workgroup leaves the list once every pixel has stopped.
-// The weight walk is recomputed by each of the D/128 slices of a tile; it is
-// a small fraction of the MFMA work.
+// The weight walk is recomputed by each of the D/128 slices of a tile.
 #include "common.h"
 #include "render_common.h"
 
 namespace qr {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kDC = 128;               // feature columns per workgroup
-constexpr int kGB = 32;                // list entries per batch
-constexpr int kFStride = kDC + 16;     // LDS row stride (floats): rows land 16 banks apart
-constexpr int kWStride = kTilePix + 16;
+constexpr int kDC = 128;            // feature columns per workgroup
+constexpr int kGB = 32;             // list entries per batch (= MFMA K)
+constexpr int kKS = kGB + 8;        // LDS stride (bf16) of a 32-entry row: 80 B
+
+__device__ __forceinline__ void split_bf16(float x, __bf16* hi, __bf16* lo) {
+  const __bf16 h = static_cast<__bf16>(x);
+  *hi = h;
+  *lo = static_cast<__bf16>(x - static_cast<float>(h));
+}
 
 template <int DT>
 __global__ void __launch_bounds__(kTilePix)
@@ -34,8 +45,12 @@ render_dense_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
                     const void* __restrict__ feats, const float* __restrict__ scale, int dim,
                     float* __restrict__ out, float* __restrict__ T_final,
                     int32_t* __restrict__ n_contrib) {
-  __shared__ float s_F[kGB * kFStride];
-  __shared__ float s_W[kGB * kWStride];
+  constexpr bool kSplitF = DT != QR_BF16;
+  // A operand rows: one per pixel, 32 entries; B operand rows: one per column
+  __shared__ __attribute__((aligned(16))) __bf16 s_Ahi[kTilePix * kKS];
+  __shared__ __attribute__((aligned(16))) __bf16 s_Alo[kTilePix * kKS];
+  __shared__ __attribute__((aligned(16))) __bf16 s_Bhi[kDC * kKS];
+  __shared__ __attribute__((aligned(16))) __bf16 s_Blo[kSplitF ? kDC * kKS : 8];
   __shared__ float2 s_mean[kGB];
   __shared__ float4 s_co[kGB];
   __shared__ int s_gid[kGB];
@@ -75,14 +90,27 @@ render_dense_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
       s_co[tid] = conic_opacity[g];
     }
     __syncthreads();
-    // feature slice of the batch, decoded to float32; missing rows are zero
+    // feature slice of the batch, split to bf16, stored column-major (B
+    // operand: 8 consecutive entries of one column per lane); missing rows
+    // are zero
     for (int e = tid; e < kGB * dc4; e += kTilePix) {
       const int r = e / dc4, c4 = e - r * dc4;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (r < cnt) v = load_feat4<DT>(feats, scale, s_gid[r], dim, d0 + 4 * c4);
-      *reinterpret_cast<float4*>(&s_F[r * kFStride + 4 * c4]) = v;
+      const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int col = 4 * c4 + i;
+        if constexpr (kSplitF) {
+          split_bf16(vv[i], &s_Bhi[col * kKS + r], &s_Blo[col * kKS + r]);
+        } else {
+          s_Bhi[col * kKS + r] = static_cast<__bf16>(vv[i]);  // exact: the value is bf16
+        }
+      }
     }
     // per-pixel weights of the batch (Eq. 1), in list order
+    __bf16* arow_hi = s_Ahi + tid * kKS;
+    __bf16* arow_lo = s_Alo + tid * kKS;
     for (int j = 0; j < kGB; ++j) {
       float w = 0.f;
       if (j < cnt && !done) {
@@ -98,25 +126,34 @@ render_dense_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
           }
         }
       }
-      s_W[j * kWStride + tid] = w;
+      split_bf16(w, &arow_hi[j], &arow_lo[j]);
     }
     __syncthreads();
     // W[64 px x 32] . F[32 x dc] for this wave's 64 pixels
-    const int krow = lane >> 4;
-    const int col = lane & 15;
+    const int kq = (lane >> 4) * 8;  // this lane's 8 consecutive entries
+    const int row = lane & 15;
+    bf16x8 ahi[4], alo[4];
 #pragma unroll
-    for (int ks = 0; ks < kGB / 4; ++ks) {
-      const int k = ks * 4 + krow;
-      float a[4];
+    for (int mt = 0; mt < 4; ++mt) {
+      const int p = wave * 64 + mt * 16 + row;
+      ahi[mt] = *reinterpret_cast<const bf16x8*>(&s_Ahi[p * kKS + kq]);
+      alo[mt] = *reinterpret_cast<const bf16x8*>(&s_Alo[p * kKS + kq]);
+    }
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt) a[mt] = s_W[k * kWStride + wave * 64 + mt * 16 + col];
+    for (int nt = 0; nt < 8; ++nt) {
+      if (nt < n_nt) {
+        const int col = nt * 16 + row;
+        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(&s_Bhi[col * kKS + kq]);
 #pragma unroll
-      for (int nt = 0; nt < 8; ++nt) {
-        if (nt < n_nt) {
-          const float b = s_F[k * kFStride + nt * 16 + col];
+        for (int mt = 0; mt < 4; ++mt) {
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt], bhi, acc[mt][nt], 0, 0, 0);
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[mt], bhi, acc[mt][nt], 0, 0, 0);
+        }
+        if constexpr (kSplitF) {
+          const bf16x8 blo = *reinterpret_cast<const bf16x8*>(&s_Blo[col * kKS + kq]);
 #pragma unroll
           for (int mt = 0; mt < 4; ++mt)
-            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt], b, acc[mt][nt], 0, 0, 0);
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt], blo, acc[mt][nt], 0, 0, 0);
         }
       }
     }

@@ -19,38 +19,66 @@
 
 namespace qr {
 
-template <int DT>
-__global__ void __launch_bounds__(kTilePix)
-render_quantile_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm, int K,
-                       const uint32_t* __restrict__ tile_offsets,
-                       const uint32_t* __restrict__ sorted_gid,
-                       const float2* __restrict__ means2d, const float4* __restrict__ conic_opacity,
-                       const void* __restrict__ feats, const float* __restrict__ scale, int dim,
-                       float* __restrict__ out, float* __restrict__ T_q_out,
-                       int32_t* __restrict__ n_sel_out, int32_t* __restrict__ sel_gid_out,
-                       float* __restrict__ sel_w_out) {
-  extern __shared__ unsigned char dyn_lds[];
-  int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);                 // [256][K]
-  float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * K;  // [256][K]
-  __shared__ float2 s_mean[kTilePix];
-  __shared__ float4 s_co[kTilePix];
-  __shared__ int s_gid[kTilePix];
-  __shared__ float s_thr[QR_MAX_K + 1];
-  __shared__ float s_inv[kTilePix];
-  __shared__ int s_ns[kTilePix];
+constexpr int kViewShift = QR_BATCH_TILE_BITS;
+constexpr uint32_t kTileMask = (1u << QR_BATCH_TILE_BITS) - 1u;
 
+// LDS of one workgroup: record staging, thresholds, and each pixel's
+// selections (the [256][K] arrays live in dynamic LDS).
+constexpr int kBmWords = 256;          // bitmap of list positions < 8192
+constexpr int kUMax = 128;             // unique selected Gaussians staged per tile
+constexpr int kDCh = 64;               // feature columns staged per chunk
+constexpr int kRowStride = kDCh + 4;   // LDS row stride (floats)
+
+struct QuantileLds {
+  float2 mean[kTilePix];
+  float4 co[kTilePix];
+  int gid[kTilePix];
+  float thr[QR_MAX_K + 1];
+  float inv[kTilePix];
+  int ns[kTilePix];
+  uint32_t bm[kBmWords];
+  uint32_t wpre[kBmWords];
+  int colgid[kUMax];
+  uint32_t misc[8];
+  float rows[kUMax * kRowStride];
+};
+
+struct ViewArgs {
+  int W, H;
+  const uint32_t* __restrict__ tile_offsets;
+  const uint32_t* __restrict__ sorted_gid;
+  const float2* __restrict__ means2d;
+  const float4* __restrict__ conic_opacity;
+  const void* __restrict__ feats;
+  const float* __restrict__ scale;
+  float* __restrict__ out;
+  float* __restrict__ T_q;
+  int32_t* __restrict__ n_sel;
+};
+
+// Algorithm 1 for every pixel of one tile, then the gather-blend of the
+// selected rows. Called by all 256 threads of the workgroup; starts and ends
+// with the workgroup synchronised.
+template <int DT>
+__device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K, int dim,
+                                              const qr_params& prm, QuantileLds& L,
+                                              int* __restrict__ s_sel_gid,
+                                              float* __restrict__ s_sel_w,
+                                              int32_t* __restrict__ sel_gid_out,
+                                              float* __restrict__ sel_w_out) {
+  const int W = v.W, H = v.H;
+  const int tiles_x = (W + kTile - 1) / kTile;
   const int tid = threadIdx.x;
-  const int tile = xcd_remap(blockIdx.x, n_tiles);
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int px = tx * kTile + (tid % kTile);
   const int py = ty * kTile + (tid / kTile);
   const bool inside = px < W && py < H;
   const float pxc = px + 0.5f, pyc = py + 0.5f;
 
-  if (tid <= K) s_thr[tid] = quantile_threshold(tid + 1, K);  // s_thr[k] = t_{k+1}; s_thr[K] = 0
+  if (tid <= K) L.thr[tid] = quantile_threshold(tid + 1, K);  // thr[k] = t_{k+1}; thr[K] = 0
 
-  const int lo = static_cast<int>(tile_offsets[tile]);
-  const int hi = static_cast<int>(tile_offsets[tile + 1]);
+  const int lo = static_cast<int>(v.tile_offsets[tile]);
+  const int hi = static_cast<int>(v.tile_offsets[tile + 1]);
 
   float T = 1.f, TQ = 1.f;
   int k = 0, ns = 0;
@@ -62,24 +90,24 @@ render_quantile_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm, in
     if (__syncthreads_count(!done) == 0) break;
     const int idx = batch + tid;
     if (idx < hi) {
-      const int g = static_cast<int>(sorted_gid[idx]);
-      s_gid[tid] = g;
-      s_mean[tid] = means2d[g];
-      s_co[tid] = conic_opacity[g];
+      const int g = static_cast<int>(v.sorted_gid[idx]);
+      L.gid[tid] = g;
+      L.mean[tid] = v.means2d[g];
+      L.co[tid] = v.conic_opacity[g];
     }
     __syncthreads();
     const int cnt = min(kTilePix, hi - batch);
     for (int j = 0; j < cnt && !done; ++j) {
-      const float alpha = gauss_alpha(s_mean[j], s_co[j], pxc, pyc, prm.alpha_max);
+      const float alpha = gauss_alpha(L.mean[j], L.co[j], pxc, pyc, prm.alpha_max);
       if (alpha < prm.alpha_min) continue;  // not on this pixel's ray
       const float T_test = T * (1.f - alpha);
-      if (T_test < s_thr[k]) {  // crossing: a quantile Gaussian
-        my_gid[ns] = s_gid[j];
+      if (T_test < L.thr[k]) {  // crossing: a quantile Gaussian
+        my_gid[ns] = batch - lo + j;  // list position within the tile
         my_w[ns] = TQ * alpha;
         ++ns;
         TQ = TQ * (1.f - alpha);
         ++k;
-        while (k < K && T_test < s_thr[k]) ++k;  // thresholds crossed by the same step
+        while (k < K && T_test < L.thr[k]) ++k;  // thresholds crossed by the same step
         if (k == K) done = true;
       }
       T = T_test;
@@ -87,37 +115,102 @@ render_quantile_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm, in
   }
   if (inside) {
     const int pix = py * W + px;
-    if (T_q_out) T_q_out[pix] = TQ;
-    if (n_sel_out) n_sel_out[pix] = ns;
+    if (v.T_q) v.T_q[pix] = TQ;
+    if (v.n_sel) v.n_sel[pix] = ns;
     if (sel_gid_out) {
       for (int j = 0; j < K; ++j) {
-        sel_gid_out[static_cast<int64_t>(pix) * K + j] = j < ns ? my_gid[j] : -1;
+        sel_gid_out[static_cast<int64_t>(pix) * K + j] =
+            j < ns ? static_cast<int>(v.sorted_gid[lo + my_gid[j]]) : -1;
         sel_w_out[static_cast<int64_t>(pix) * K + j] = j < ns ? my_w[j] : 0.f;
       }
     }
   }
-  s_ns[tid] = inside ? ns : -1;
-  s_inv[tid] = ns > 0 ? 1.f / (1.f - TQ) : 0.f;
+  L.ns[tid] = inside ? ns : -1;
+  L.inv[tid] = ns > 0 ? 1.f / (1.f - TQ) : 0.f;
   __syncthreads();
 
-  // Phase 2: gather-blend. Wave w owns pixels [64 w, 64 w + 64) and takes
-  // them kPG at a time; lanes span the feature dimension. Every selected row
-  // of the kPG pixels is requested before any is accumulated (rows of pixels
-  // with fewer selections are padded with weight 0 and a valid row of the
-  // group), so each lane keeps 2 kPG independent loads in flight.
-  constexpr int kPG = 4;
+  // Phase 2: gather-blend out[p] = sum_j w_pj f_j / (1 - T^Q_p).
+  // Neighbouring pixels select mostly the same Gaussians, so the tile's
+  // distinct selected rows (usually a few dozen) are staged in LDS once per
+  // 64-column chunk and every pixel gathers from LDS; each feature row then
+  // crosses L2 once per tile instead of once per selecting pixel. Tiles with
+  // more distinct rows than fit, or selections deep in a very long list, use
+  // the same gather straight from global memory.
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  L.bm[tid] = 0u;
+  if (tid == 0) L.misc[0] = 0u;
+  __syncthreads();
+  for (int j = 0; j < ns; ++j) {
+    const int pos = my_gid[j];
+    if (pos < kBmWords * 32) atomicOr(&L.bm[pos >> 5], 1u << (pos & 31));
+    else L.misc[0] = 1u;
+  }
+  __syncthreads();
+  uint32_t n_unique;
+  L.wpre[tid] = block_scan_exclusive(__popc(L.bm[tid]), &L.misc[4], &n_unique);
+  __syncthreads();
+  if (n_unique <= static_cast<uint32_t>(kUMax) && L.misc[0] == 0u) {
+    // selections -> staged-row index; record each row's Gaussian
+    for (int j = 0; j < ns; ++j) {
+      const int pos = my_gid[j];
+      const uint32_t word = L.bm[pos >> 5];
+      const int col = static_cast<int>(L.wpre[pos >> 5] + __popc(word & ((1u << (pos & 31)) - 1u)));
+      my_gid[j] = col;
+      L.colgid[col] = static_cast<int>(v.sorted_gid[lo + pos]);  // same value from every writer
+    }
+    __syncthreads();
+    for (int d0 = 0; d0 < dim; d0 += kDCh) {
+      const int cw = min(kDCh, dim - d0);   // multiple of 16
+      const int lpp = cw >> 2;              // lanes per pixel (float4 each)
+      const int ppw = 64 / lpp;             // pixels per wave step (lanes beyond idle)
+      const int sub = lane / lpp, c4 = lane - sub * lpp;
+      for (int e = tid; e < static_cast<int>(n_unique) * lpp; e += kTilePix) {
+        const int r = e / lpp, q4 = e - r * lpp;
+        *reinterpret_cast<float4*>(&L.rows[r * kRowStride + 4 * q4]) =
+            load_feat4<DT>(v.feats, v.scale, L.colgid[r], dim, d0 + 4 * q4);
+      }
+      __syncthreads();
+      for (int pb = wave * 64; pb < wave * 64 + 64; pb += ppw) {
+        const int p = pb + sub;
+        if (sub >= ppw || p >= wave * 64 + 64) continue;
+        const int n = L.ns[p];
+        if (n < 0) continue;  // outside the image
+        const int* cl = s_sel_gid + p * K;
+        const float* wl = s_sel_w + p * K;
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int j = 0; j < n; ++j) {
+          const float4 f = *reinterpret_cast<const float4*>(&L.rows[cl[j] * kRowStride + 4 * c4]);
+          const float w = wl[j];
+          acc.x += w * f.x;
+          acc.y += w * f.y;
+          acc.z += w * f.z;
+          acc.w += w * f.w;
+        }
+        const float inv = L.inv[p];
+        const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
+        float4* dst = reinterpret_cast<float4*>(v.out + (static_cast<int64_t>(gy) * W + gx) * dim + d0) + c4;
+        store_stream(dst, make_float4(acc.x * inv, acc.y * inv, acc.z * inv, acc.w * inv));
+      }
+      __syncthreads();
+    }
+    return;
+  }
+
+  // Fallback: wave w owns pixels [64 w, 64 w + 64), kPG at a time, lanes
+  // across D, every selected row of the kPG pixels requested from global
+  // memory before any is accumulated.
+  constexpr int kPG = 4;
   const int dim4 = dim >> 2;
   for (int p0 = wave * 64; p0 < wave * 64 + 64; p0 += kPG) {
     int n[kPG];
     int nmax = 0, safe = 0;
 #pragma unroll
     for (int q = 0; q < kPG; ++q) {
-      n[q] = s_ns[p0 + q];
+      n[q] = L.ns[p0 + q];
       if (n[q] > nmax) {
         nmax = n[q];
-        safe = s_sel_gid[(p0 + q) * K];
+        safe = static_cast<int>(v.sorted_gid[lo + s_sel_gid[(p0 + q) * K]]);
       }
     }
     for (int c = lane; c < dim4; c += 64) {
@@ -130,9 +223,9 @@ render_quantile_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm, in
 #pragma unroll
         for (int q = 0; q < kPG; ++q) {
           const bool ok = j < n[q];
-          const int g = ok ? s_sel_gid[(p0 + q) * K + j] : safe;
+          const int g = ok ? static_cast<int>(v.sorted_gid[lo + s_sel_gid[(p0 + q) * K + j]]) : safe;
           w[q] = ok ? s_sel_w[(p0 + q) * K + j] : 0.f;
-          f[q] = load_feat4<DT>(feats, scale, g, dim, 4 * c);
+          f[q] = load_feat4<DT>(v.feats, v.scale, g, dim, 4 * c);
         }
 #pragma unroll
         for (int q = 0; q < kPG; ++q) {
@@ -147,13 +240,57 @@ render_quantile_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm, in
         if (n[q] < 0) continue;  // outside the image
         const int p = p0 + q;
         const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
-        float4* dst = reinterpret_cast<float4*>(out + (static_cast<int64_t>(gy) * W + gx) * dim);
-        const float inv = s_inv[p];
+        float4* dst = reinterpret_cast<float4*>(v.out + (static_cast<int64_t>(gy) * W + gx) * dim);
+        const float inv = L.inv[p];
         store_stream(dst + c, make_float4(acc[q].x * inv, acc[q].y * inv, acc[q].z * inv, acc[q].w * inv));
       }
     }
   }
+  __syncthreads();
 }
+
+template <int DT>
+__global__ void __launch_bounds__(kTilePix)
+render_quantile_kernel(ViewArgs v, int n_tiles, qr_params prm, int K, int dim,
+                       int32_t* __restrict__ sel_gid_out, float* __restrict__ sel_w_out) {
+  extern __shared__ unsigned char dyn_lds[];
+  __shared__ QuantileLds L;
+  int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);                 // [256][K]
+  float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * K;  // [256][K]
+  quantile_tile<DT>(v, xcd_remap(blockIdx.x, n_tiles), K, dim, prm, L, s_sel_gid, s_sel_w,
+                    sel_gid_out, sel_w_out);
+}
+
+// Many views in one persistent launch. Workgroups take (view, tile) items
+// from `schedule` in order through an atomic counter until it is exhausted;
+// every workgroup leaves once the counter passes n_items.
+template <int DT>
+__global__ void __launch_bounds__(kTilePix)
+render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t* __restrict__ schedule,
+                               int64_t n_items, uint32_t* __restrict__ counter, qr_params prm,
+                               int K, int dim) {
+  extern __shared__ unsigned char dyn_lds[];
+  __shared__ QuantileLds L;
+  __shared__ uint32_t s_item;
+  int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);
+  float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * K;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t item = s_item;
+    if (item >= n_items) break;
+    const uint32_t packed = schedule[item];
+    const qr_view& qv = views[packed >> kViewShift];
+    ViewArgs v{qv.width, qv.height, qv.tile_offsets, qv.sorted_gid,
+               reinterpret_cast<const float2*>(qv.means2d),
+               reinterpret_cast<const float4*>(qv.conic_opacity), qv.features,
+               qv.feature_scale, qv.out, qv.T_q, qv.n_sel};
+    quantile_tile<DT>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
+                      nullptr, nullptr);
+  }
+}
+
+__global__ void reset_counter_kernel(uint32_t* __restrict__ c) { *c = 0u; }
 
 }  // namespace qr
 
@@ -175,14 +312,15 @@ extern "C" int qr_render_quantile(void* stream, int32_t width, int32_t height,
   const int tiles_x = static_cast<int>(ceil_div(width, kTile));
   const int tiles_y = static_cast<int>(ceil_div(height, kTile));
   const int n_tiles = tiles_x * tiles_y;
+  (void)tiles_x;
   const size_t lds = static_cast<size_t>(kTilePix) * K * (sizeof(int) + sizeof(float));
   hipStream_t s = as_stream(stream);
-#define QR_LAUNCH(DT)                                                                             \
-  hipLaunchKernelGGL(render_quantile_kernel<DT>, dim3(n_tiles), dim3(kTilePix), lds, s, width,    \
-                     height, tiles_x, n_tiles, *prm, K, tile_offsets, sorted_gid,                 \
-                     reinterpret_cast<const float2*>(means2d),                                    \
-                     reinterpret_cast<const float4*>(conic_opacity), features, feature_scale, dim, \
-                     out, T_q, n_sel, sel_gid, sel_w)
+  const ViewArgs v{width, height, tile_offsets, sorted_gid, reinterpret_cast<const float2*>(means2d),
+                   reinterpret_cast<const float4*>(conic_opacity), features, feature_scale, out, T_q,
+                   n_sel};
+#define QR_LAUNCH(DT)                                                                              \
+  hipLaunchKernelGGL(render_quantile_kernel<DT>, dim3(n_tiles), dim3(kTilePix), lds, s, v, n_tiles, \
+                     *prm, K, dim, sel_gid, sel_w)
   switch (dtype) {
     case QR_F32: QR_LAUNCH(QR_F32); break;
     case QR_BF16: QR_LAUNCH(QR_BF16); break;
@@ -190,4 +328,43 @@ extern "C" int qr_render_quantile(void* stream, int32_t width, int32_t height,
   }
 #undef QR_LAUNCH
   return check_launch("qr_render_quantile");
+}
+
+extern "C" int qr_render_quantile_batched(void* stream, int32_t n_views, const qr_view* views,
+                                          const qr_params* prm, int32_t K, int32_t dtype,
+                                          int32_t dim, const uint32_t* schedule, int64_t n_items,
+                                          int32_t n_workgroups, void* workspace,
+                                          size_t workspace_bytes) {
+  if (n_views <= 0 || n_views > (1 << (32 - kViewShift)))
+    return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: n_views = %d out of range", n_views);
+  if (!views || !schedule || !workspace || !prm)
+    return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: null pointer");
+  if (workspace_bytes < sizeof(uint32_t))
+    return fail(QR_ERR_CAPACITY, "qr_render_quantile_batched: workspace needs 4 bytes");
+  if (n_items < 0 || n_items >= (1ll << 32))
+    return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: bad item count");
+  if (n_workgroups <= 0) return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: n_workgroups <= 0");
+  if (K < 1 || K > QR_MAX_K)
+    return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile_batched: K = %d outside [1, %d]", K, QR_MAX_K);
+  if (dtype != QR_F32 && dtype != QR_BF16 && dtype != QR_FP8_E4M3)
+    return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile_batched: unknown dtype %d", dtype);
+  if (dim <= 0 || dim % 16 != 0 || dim > QR_MAX_DIM)
+    return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile_batched: dim = %d", dim);
+  if (!(prm->alpha_min > 0.f) || !(prm->alpha_max >= prm->alpha_min) || !(prm->alpha_max < 1.f))
+    return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: need 0 < alpha_min <= alpha_max < 1");
+  if (n_items == 0) return QR_OK;
+  hipStream_t s = as_stream(stream);
+  auto* counter = static_cast<uint32_t*>(workspace);
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+  const size_t lds = static_cast<size_t>(kTilePix) * K * (sizeof(int) + sizeof(float));
+#define QR_LAUNCH(DT)                                                                             \
+  hipLaunchKernelGGL(render_quantile_batched_kernel<DT>, dim3(n_workgroups), dim3(kTilePix), lds, \
+                     s, views, schedule, n_items, counter, *prm, K, dim)
+  switch (dtype) {
+    case QR_F32: QR_LAUNCH(QR_F32); break;
+    case QR_BF16: QR_LAUNCH(QR_BF16); break;
+    default: QR_LAUNCH(QR_FP8_E4M3); break;
+  }
+#undef QR_LAUNCH
+  return check_launch("qr_render_quantile_batched");
 }

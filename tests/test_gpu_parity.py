@@ -193,6 +193,35 @@ def test_render_parity_ragged_image(qr, K):
     assert res["q"]["n_sel"].max() <= K
 
 
+@pytest.mark.parametrize("dim", [48, 80])
+def test_render_parity_feature_width_not_multiple_of_64(qr, dim):
+    """Feature widths that leave a partial staged column chunk."""
+    sc = synth.make_tiny(12, n=2500, dim=dim)
+    cam = synth.tiny_camera(72)
+    res = gpu_pipeline(qr, sc, cam, 8)
+    ors = oracle_renders(res, sc.features.astype(np.float64), 72, 72, 8)
+    check_all(res, ors, 72, 72)
+
+
+def test_render_parity_many_distinct_selections(qr):
+    """30,000 pixel-sized, nearly opaque Gaussians: every pixel selects its
+    own few, so a tile holds hundreds of distinct selected Gaussians - more
+    than the per-tile LDS staging takes - and the direct gather is used."""
+    rng = np.random.default_rng(21)
+    n = 30_000
+    sc = synth.Scene(rng.uniform(-1.0, 1.0, (n, 3)).astype(np.float32),
+                     np.full((n, 3), 0.004, np.float32), synth.scenes._unit_quats(rng, n),
+                     rng.uniform(0.5, 0.99, n).astype(np.float32),
+                     rng.standard_normal((n, 32)).astype(np.float32))
+    cam = synth.tiny_camera(64)
+    res = gpu_pipeline(qr, sc, cam, 8)
+    uniq = [len(set(res["q"]["sel_gid"][y:y + 16, x:x + 16].ravel()) - {-1})
+            for y in range(0, 64, 16) for x in range(0, 64, 16)]
+    assert max(uniq) > 128, uniq
+    ors = oracle_renders(res, sc.features.astype(np.float64), 64, 64, 8)
+    check_all(res, ors, 64, 64)
+
+
 @pytest.fixture(scope="module")
 def room_res(qr):
     sc = synth.make_room(200_000, 1, dim=512)
