@@ -4,8 +4,8 @@
 // the pixel; as in 3D-GS it is built per 16x16 tile. Instead of one global
 // sort of (tile, depth) keys this is a bucket sort by tile followed by an
 // independent sort of each tile's bucket in LDS:
-//   1. count: exclusive scan of tiles_touched gives each Gaussian's pair
-//      range; one thread per pair then increments its tile's counter;
+//   1. count: every (Gaussian, covered tile) pair increments its tile's
+//      counter (each wave spreads one Gaussian's tiles over its lanes);
 //   2. exclusive scan of the counts -> tile_offsets (CSR) and the pair count;
 //   3. scatter: each pair claims a slot in its tile's bucket with an atomic
 //      cursor and stores the 64-bit key (float bits of depth << 32 | id);
@@ -107,52 +107,49 @@ zero_u32_kernel(uint32_t* __restrict__ a, int64_t n) {
   for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) a[i] = 0u;
 }
 
-// One thread per (Gaussian, tile) pair: the pair's Gaussian is found by
-// binary search in the exclusive scan of tiles_touched (pair_off[0..n]), so a
-// Gaussian that covers a thousand tiles costs a thousand threads rather than a
-// thousand serial iterations of one thread. Grid-stride over the pair count
-// read from device memory.
-__device__ __forceinline__ void pair_tile(int64_t k, int64_t n, const uint32_t* __restrict__ pair_off,
-                                          const int4* __restrict__ rect, int tiles_x, int64_t* gid,
-                                          int* tile) {
-  int64_t lo = 0, hi = n;  // find the last i with pair_off[i] <= k
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (pair_off[mid] <= static_cast<uint32_t>(k)) lo = mid; else hi = mid;
-  }
-  const int4 r = rect[lo];
-  const int w = r.z - r.x;
-  const int l = static_cast<int>(k - pair_off[lo]);
-  *gid = lo;
-  *tile = (r.y + l / w) * tiles_x + r.x + l % w;
-}
-
+// Each wave takes 64 consecutive Gaussians and visits them one after the
+// other; the covered tiles of the current Gaussian are spread over the 64
+// lanes, so a Gaussian that covers a thousand tiles costs sixteen lane-rounds
+// instead of a thousand serial iterations of one thread, and no per-pair
+// index (and no scan of per-Gaussian pair counts) is needed.
+template <bool kScatter>
 __global__ void __launch_bounds__(256)
-tile_count_kernel(int64_t n, const uint32_t* __restrict__ pair_off, const int4* __restrict__ rect,
-                  int tiles_x, uint32_t* __restrict__ cnt) {
-  const int64_t P = pair_off[n];
-  for (int64_t k = blockIdx.x * 256LL + threadIdx.x; k < P; k += 256LL * gridDim.x) {
-    int64_t g;
-    int t;
-    pair_tile(k, n, pair_off, rect, tiles_x, &g, &t);
-    atomicAdd(&cnt[t], 1u);
+tile_pairs_kernel(int64_t n, const int4* __restrict__ rect, const uint32_t* __restrict__ touched,
+                  const float* __restrict__ depth, int tiles_x, uint32_t* __restrict__ cnt,
+                  const uint32_t* __restrict__ offsets, int64_t capacity,
+                  unsigned long long* __restrict__ bucket) {
+  const int lane = threadIdx.x & 63;
+  const int64_t base = (blockIdx.x * 256LL + threadIdx.x) - lane;  // first Gaussian of this wave
+  const int64_t mine = base + lane;
+  uint32_t my_cnt = 0;
+  int4 my_r = make_int4(0, 0, 0, 0);
+  uint32_t my_d = 0;
+  if (mine < n) {
+    my_cnt = touched[mine];
+    if (my_cnt) {
+      my_r = rect[mine];
+      if (kScatter) my_d = __float_as_uint(depth[mine]);
+    }
   }
-}
-
-__global__ void __launch_bounds__(256)
-tile_scatter_kernel(int64_t n, const uint32_t* __restrict__ pair_off, const int4* __restrict__ rect,
-                    const float* __restrict__ depth, int tiles_x,
-                    const uint32_t* __restrict__ offsets, uint32_t* __restrict__ cursor,
-                    int64_t capacity, unsigned long long* __restrict__ bucket) {
-  const int64_t P = pair_off[n];
-  for (int64_t k = blockIdx.x * 256LL + threadIdx.x; k < P; k += 256LL * gridDim.x) {
-    int64_t g;
-    int t;
-    pair_tile(k, n, pair_off, rect, tiles_x, &g, &t);
-    const int64_t slot = static_cast<int64_t>(offsets[t]) + atomicAdd(&cursor[t], 1u);
-    if (slot < capacity)
-      bucket[slot] = (static_cast<unsigned long long>(__float_as_uint(depth[g])) << 32) |
-                     static_cast<uint32_t>(g);
+  unsigned long long todo = __ballot(my_cnt != 0);
+  while (todo) {
+    const int j = __ffsll(static_cast<long long>(todo)) - 1;
+    todo &= todo - 1;
+    const uint32_t c = __shfl(my_cnt, j, 64);
+    const int rx = __shfl(my_r.x, j, 64), ry = __shfl(my_r.y, j, 64), rz = __shfl(my_r.z, j, 64);
+    const int w = rz - rx;
+    const unsigned long long key = kScatter
+        ? ((static_cast<unsigned long long>(__shfl(my_d, j, 64)) << 32) | static_cast<uint32_t>(base + j))
+        : 0ull;
+    for (uint32_t k = lane; k < c; k += 64) {
+      const int t = (ry + static_cast<int>(k) / w) * tiles_x + rx + static_cast<int>(k) % w;
+      if (kScatter) {
+        const int64_t slot = static_cast<int64_t>(offsets[t]) + atomicAdd(&cnt[t], 1u);
+        if (slot < capacity) bucket[slot] = key;
+      } else {
+        atomicAdd(&cnt[t], 1u);
+      }
+    }
   }
 }
 
@@ -269,16 +266,14 @@ tile_sort_kernel(int n_tiles, const uint32_t* __restrict__ offsets, int64_t capa
 
 // ---- workspace layout --------------------------------------------------------
 struct Layout {
-  size_t pair_off, part_n, cnt, cursor, part, bucket, scratch, bytes;
+  size_t cnt, cursor, part, bucket, scratch, bytes;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-static Layout layout(int64_t n, int64_t n_tiles, int64_t capacity) {
+static Layout layout(int64_t n_tiles, int64_t capacity) {
   Layout L{};
   size_t o = 0;
-  L.pair_off = o; o = align256(o + sizeof(uint32_t) * (n + 1));
-  L.part_n = o;   o = align256(o + sizeof(uint32_t) * (scan_parts(n) + 1));
   L.cnt = o;     o = align256(o + sizeof(uint32_t) * (n_tiles + 1));
   L.cursor = o;  o = align256(o + sizeof(uint32_t) * (n_tiles + 1));
   L.part = o;    o = align256(o + sizeof(uint32_t) * (scan_parts(n_tiles) + 1));
@@ -303,7 +298,7 @@ extern "C" int qr_bin_sort_workspace_size(int64_t n, int32_t tiles_x, int32_t ti
   if (!bytes) return fail(QR_ERR_INVALID_ARG, "qr_bin_sort_workspace_size: null result pointer");
   if (n < 0 || capacity < 0 || tiles_x <= 0 || tiles_y <= 0)
     return fail(QR_ERR_INVALID_ARG, "qr_bin_sort_workspace_size: bad sizes");
-  *bytes = layout(n, static_cast<int64_t>(tiles_x) * tiles_y, capacity).bytes;
+  *bytes = layout(static_cast<int64_t>(tiles_x) * tiles_y, capacity).bytes;
   return QR_OK;
 }
 
@@ -323,15 +318,13 @@ extern "C" int qr_bin_sort(void* stream, int64_t n, int32_t tiles_x, int32_t til
   if (n > 0 && (!tile_rect || !tiles_touched || !depth))
     return fail(QR_ERR_INVALID_ARG, "qr_bin_sort: null input pointer");
   if (capacity > 0 && !sorted_gid) return fail(QR_ERR_INVALID_ARG, "qr_bin_sort: null sorted_gid");
-  const Layout L = layout(n, n_tiles, capacity);
+  const Layout L = layout(n_tiles, capacity);
   if (workspace_bytes < L.bytes)
     return fail(QR_ERR_CAPACITY, "qr_bin_sort: workspace needs %zu bytes, got %zu", L.bytes,
                 workspace_bytes);
 
   hipStream_t s = as_stream(stream);
   char* ws = static_cast<char*>(workspace);
-  auto* pair_off = reinterpret_cast<uint32_t*>(ws + L.pair_off);
-  auto* part_n = reinterpret_cast<uint32_t*>(ws + L.part_n);
   auto* cnt = reinterpret_cast<uint32_t*>(ws + L.cnt);
   auto* cursor = reinterpret_cast<uint32_t*>(ws + L.cursor);
   auto* part = reinterpret_cast<uint32_t*>(ws + L.part);
@@ -342,22 +335,16 @@ extern "C" int qr_bin_sort(void* stream, int64_t n, int32_t tiles_x, int32_t til
   const int64_t zero_n = static_cast<int64_t>((L.part - L.cnt) / sizeof(uint32_t));
   hipLaunchKernelGGL(zero_u32_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(ceil_div(zero_n, 256), 1024))),
                      dim3(256), 0, s, cnt, zero_n);
-  // pairs per Gaussian -> pair offsets (pair_off[n] = pair count)
-  if (n > 0) {
-    scan_exclusive(tiles_touched, pair_off, n, part_n, nullptr, s);
-    // grid-stride kernels over the pairs; the grid is sized by the capacity
-    const unsigned pblocks = static_cast<unsigned>(
-        std::min<int64_t>(std::max<int64_t>(ceil_div(capacity, 256), 1), 8192));
-    hipLaunchKernelGGL(tile_count_kernel, dim3(pblocks), dim3(256), 0, s, n, pair_off,
-                       reinterpret_cast<const int4*>(tile_rect), tiles_x, cnt);
-    scan_exclusive(cnt, tile_offsets, n_tiles, part, total_pairs, s);
-    if (capacity > 0)
-      hipLaunchKernelGGL(tile_scatter_kernel, dim3(pblocks), dim3(256), 0, s, n, pair_off,
-                         reinterpret_cast<const int4*>(tile_rect), depth, tiles_x, tile_offsets,
-                         cursor, capacity, bucket);
-  } else {
-    scan_exclusive(cnt, tile_offsets, n_tiles, part, total_pairs, s);
-  }
+  const unsigned gblocks = static_cast<unsigned>(std::max<int64_t>(ceil_div(n, 256), 1));
+  if (n > 0)
+    hipLaunchKernelGGL(tile_pairs_kernel<false>, dim3(gblocks), dim3(256), 0, s, n,
+                       reinterpret_cast<const int4*>(tile_rect), tiles_touched, depth, tiles_x, cnt,
+                       nullptr, capacity, nullptr);
+  scan_exclusive(cnt, tile_offsets, n_tiles, part, total_pairs, s);
+  if (n > 0 && capacity > 0)
+    hipLaunchKernelGGL(tile_pairs_kernel<true>, dim3(gblocks), dim3(256), 0, s, n,
+                       reinterpret_cast<const int4*>(tile_rect), tiles_touched, depth, tiles_x,
+                       cursor, tile_offsets, capacity, bucket);
   if (capacity > 0)
     hipLaunchKernelGGL(tile_sort_kernel, dim3(static_cast<unsigned>(n_tiles)), dim3(256), 0, s,
                        static_cast<int>(n_tiles), tile_offsets, capacity, bits_for(n), bucket,

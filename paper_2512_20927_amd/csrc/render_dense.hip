@@ -38,7 +38,7 @@ __device__ __forceinline__ void split_bf16(float x, __bf16* hi, __bf16* lo) {
 }
 
 template <int DT>
-__global__ void __launch_bounds__(kTilePix)
+__global__ void __launch_bounds__(kTilePix, 2)
 render_dense_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
                     const uint32_t* __restrict__ tile_offsets, const uint32_t* __restrict__ sorted_gid,
                     const float2* __restrict__ means2d, const float4* __restrict__ conic_opacity,
@@ -111,6 +111,7 @@ render_dense_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
     // per-pixel weights of the batch (Eq. 1), in list order
     __bf16* arow_hi = s_Ahi + tid * kKS;
     __bf16* arow_lo = s_Alo + tid * kKS;
+    bool any_w = false;
     for (int j = 0; j < kGB; ++j) {
       float w = 0.f;
       if (j < cnt && !done) {
@@ -126,9 +127,14 @@ render_dense_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
           }
         }
       }
+      any_w |= w != 0.f;
       split_bf16(w, &arow_hi[j], &arow_lo[j]);
     }
+    // a wave whose 64 pixels take nothing from this batch skips its MFMAs
+    // (thread tid is pixel tid, so wave w's pixels are exactly its A rows)
+    const bool wave_busy = __ballot(any_w) != 0ull;
     __syncthreads();
+    if (!wave_busy) continue;
     // W[64 px x 32] . F[32 x dc] for this wave's 64 pixels
     const int kq = (lane >> 4) * 8;  // this lane's 8 consecutive entries
     const int row = lane & 15;

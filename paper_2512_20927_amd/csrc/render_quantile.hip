@@ -8,12 +8,14 @@
 // LDS. A pixel is done once all K thresholds are consumed (the paper's stop
 // test T_test < 1/(K+1) is the same event), and the whole workgroup leaves the
 // list as soon as every pixel is done.
-// Phase 2 (gather-blend): each wave takes four pixels at a time, its lanes
-// spanning the feature dimension; the <= K selected feature rows of all four
-// are requested together (mostly L2 hits: neighbouring pixels select the same
-// Gaussians), accumulated in float32, scaled by 1 / (1 - T^Q), and streamed
-// to the [H, W, D] map with non-temporal stores. The map write is the dominant HBM
-// traffic of the whole pipeline.
+// Phase 2 (gather-blend): pixels are gathered four at a time (a row segment
+// of the tile) with the lanes of a wave spanning the feature dimension. The
+// four pixels' selection lists are first merged into their distinct
+// selections, each carrying the four weights, so every distinct feature row
+// is loaded once per group (mostly from L2: neighbouring pixels select the
+// same Gaussians); rows are accumulated in float32, scaled by 1 / (1 - T^Q)
+// and streamed to the [H, W, D] map with non-temporal stores. The map write
+// is the dominant HBM traffic of the whole pipeline.
 #include "common.h"
 #include "render_common.h"
 
@@ -24,23 +26,22 @@ constexpr uint32_t kTileMask = (1u << QR_BATCH_TILE_BITS) - 1u;
 
 // LDS of one workgroup: record staging, thresholds, and each pixel's
 // selections (the [256][K] arrays live in dynamic LDS).
-constexpr int kBmWords = 256;          // bitmap of list positions < 8192
-constexpr int kUMax = 128;             // unique selected Gaussians staged per tile
-constexpr int kDCh = 64;               // feature columns staged per chunk
-constexpr int kRowStride = kDCh + 4;   // LDS row stride (floats)
+constexpr int kPG = 4;                     // pixels gathered together
+constexpr int kGroups = kTilePix / kPG;    // 64 pixel groups per tile
+#ifndef QR_UCAP
+#define QR_UCAP 16
+#endif
+constexpr int kUCap = QR_UCAP;             // distinct selections kept per group
 
 struct QuantileLds {
   float2 mean[kTilePix];
   float4 co[kTilePix];
-  int gid[kTilePix];
   float thr[QR_MAX_K + 1];
   float inv[kTilePix];
   int ns[kTilePix];
-  uint32_t bm[kBmWords];
-  uint32_t wpre[kBmWords];
-  int colgid[kUMax];
-  uint32_t misc[8];
-  float rows[kUMax * kRowStride];
+  int unum[kGroups];                       // distinct entries per group, -1 if over kUCap
+  int ugid[kGroups * kUCap];
+  float4 uw[kGroups * kUCap];              // the group's four pixel weights, x = first pixel
 };
 
 struct ViewArgs {
@@ -83,15 +84,16 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
   float T = 1.f, TQ = 1.f;
   int k = 0, ns = 0;
   bool done = !inside;
-  int* my_gid = s_sel_gid + tid * K;
-  float* my_w = s_sel_w + tid * K;
+  const int KP = (K + 3) & ~3;  // selection row stride: 16-byte aligned rows
+  int* s_sel_pos = s_sel_gid;  // selections are kept as tile-list positions
+  int* my_pos = s_sel_pos + tid * KP;
+  float* my_w = s_sel_w + tid * KP;
 
   for (int batch = lo; batch < hi; batch += kTilePix) {
     if (__syncthreads_count(!done) == 0) break;
     const int idx = batch + tid;
     if (idx < hi) {
       const int g = static_cast<int>(v.sorted_gid[idx]);
-      L.gid[tid] = g;
       L.mean[tid] = v.means2d[g];
       L.co[tid] = v.conic_opacity[g];
     }
@@ -102,7 +104,7 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
       if (alpha < prm.alpha_min) continue;  // not on this pixel's ray
       const float T_test = T * (1.f - alpha);
       if (T_test < L.thr[k]) {  // crossing: a quantile Gaussian
-        my_gid[ns] = batch - lo + j;  // list position within the tile
+        my_pos[ns] = batch + j;
         my_w[ns] = TQ * alpha;
         ++ns;
         TQ = TQ * (1.f - alpha);
@@ -120,7 +122,7 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
     if (sel_gid_out) {
       for (int j = 0; j < K; ++j) {
         sel_gid_out[static_cast<int64_t>(pix) * K + j] =
-            j < ns ? static_cast<int>(v.sorted_gid[lo + my_gid[j]]) : -1;
+            j < ns ? static_cast<int>(v.sorted_gid[my_pos[j]]) : -1;
         sel_w_out[static_cast<int64_t>(pix) * K + j] = j < ns ? my_w[j] : 0.f;
       }
     }
@@ -129,80 +131,98 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
   L.inv[tid] = ns > 0 ? 1.f / (1.f - TQ) : 0.f;
   __syncthreads();
 
-  // Phase 2: gather-blend out[p] = sum_j w_pj f_j / (1 - T^Q_p).
-  // Neighbouring pixels select mostly the same Gaussians, so the tile's
-  // distinct selected rows (usually a few dozen) are staged in LDS once per
-  // 64-column chunk and every pixel gathers from LDS; each feature row then
-  // crosses L2 once per tile instead of once per selecting pixel. Tiles with
-  // more distinct rows than fit, or selections deep in a very long list, use
-  // the same gather straight from global memory.
+  // Phase 2: gather-blend out[p] = sum_j w_pj f_j / (1 - T^Q_p). Pixels
+  // are gathered four at a time (a row segment of the tile), lanes across D.
+  // Adjacent pixels select mostly the same Gaussians, so each group's four
+  // selection lists (ordered by list position) are first merged into its
+  // distinct selections, each carrying the four pixels' weights (0 where a
+  // pixel did not select it): every distinct feature row is then loaded once
+  // per group instead of once per selecting pixel. A group with more than
+  // kUCap distinct selections gathers pixel by pixel.
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  L.bm[tid] = 0u;
-  if (tid == 0) L.misc[0] = 0u;
-  __syncthreads();
-  for (int j = 0; j < ns; ++j) {
-    const int pos = my_gid[j];
-    if (pos < kBmWords * 32) atomicOr(&L.bm[pos >> 5], 1u << (pos & 31));
-    else L.misc[0] = 1u;
-  }
-  __syncthreads();
-  uint32_t n_unique;
-  L.wpre[tid] = block_scan_exclusive(__popc(L.bm[tid]), &L.misc[4], &n_unique);
-  __syncthreads();
-  if (n_unique <= static_cast<uint32_t>(kUMax) && L.misc[0] == 0u) {
-    // selections -> staged-row index; record each row's Gaussian
-    for (int j = 0; j < ns; ++j) {
-      const int pos = my_gid[j];
-      const uint32_t word = L.bm[pos >> 5];
-      const int col = static_cast<int>(L.wpre[pos >> 5] + __popc(word & ((1u << (pos & 31)) - 1u)));
-      my_gid[j] = col;
-      L.colgid[col] = static_cast<int>(v.sorted_gid[lo + pos]);  // same value from every writer
+  if (tid < kGroups) {
+    const int p0 = tid * kPG;
+    int n[kPG], idx[kPG];
+#pragma unroll
+    for (int q = 0; q < kPG; ++q) {
+      n[q] = max(L.ns[p0 + q], 0);
+      idx[q] = 0;
     }
-    __syncthreads();
-    for (int d0 = 0; d0 < dim; d0 += kDCh) {
-      const int cw = min(kDCh, dim - d0);   // multiple of 16
-      const int lpp = cw >> 2;              // lanes per pixel (float4 each)
-      const int ppw = 64 / lpp;             // pixels per wave step (lanes beyond idle)
-      const int sub = lane / lpp, c4 = lane - sub * lpp;
-      for (int e = tid; e < static_cast<int>(n_unique) * lpp; e += kTilePix) {
-        const int r = e / lpp, q4 = e - r * lpp;
-        *reinterpret_cast<float4*>(&L.rows[r * kRowStride + 4 * q4]) =
-            load_feat4<DT>(v.feats, v.scale, L.colgid[r], dim, d0 + 4 * q4);
+    int cnt = 0;
+    for (;;) {
+      int best = 0x7fffffff;
+#pragma unroll
+      for (int q = 0; q < kPG; ++q)
+        if (idx[q] < n[q]) best = min(best, s_sel_pos[(p0 + q) * KP + idx[q]]);
+      if (best == 0x7fffffff) break;
+      if (cnt == kUCap) {
+        cnt = -1;
+        break;
       }
-      __syncthreads();
-      for (int pb = wave * 64; pb < wave * 64 + 64; pb += ppw) {
-        const int p = pb + sub;
-        if (sub >= ppw || p >= wave * 64 + 64) continue;
-        const int n = L.ns[p];
-        if (n < 0) continue;  // outside the image
-        const int* cl = s_sel_gid + p * K;
-        const float* wl = s_sel_w + p * K;
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int j = 0; j < n; ++j) {
-          const float4 f = *reinterpret_cast<const float4*>(&L.rows[cl[j] * kRowStride + 4 * c4]);
-          const float w = wl[j];
-          acc.x += w * f.x;
-          acc.y += w * f.y;
-          acc.z += w * f.z;
-          acc.w += w * f.w;
+      float wq[kPG];
+#pragma unroll
+      for (int q = 0; q < kPG; ++q) {
+        wq[q] = 0.f;
+        if (idx[q] < n[q] && s_sel_pos[(p0 + q) * KP + idx[q]] == best) {
+          wq[q] = s_sel_w[(p0 + q) * KP + idx[q]];
+          ++idx[q];
         }
-        const float inv = L.inv[p];
-        const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
-        float4* dst = reinterpret_cast<float4*>(v.out + (static_cast<int64_t>(gy) * W + gx) * dim + d0) + c4;
-        store_stream(dst, make_float4(acc.x * inv, acc.y * inv, acc.z * inv, acc.w * inv));
       }
-      __syncthreads();
+      L.ugid[tid * kUCap + cnt] = best;  // position for now
+      L.uw[tid * kUCap + cnt] = make_float4(wq[0], wq[1], wq[2], wq[3]);
+      ++cnt;
     }
-    return;
+    L.unum[tid] = cnt;
+    // positions -> Gaussian ids (independent loads)
+    for (int e = 0; e < cnt; ++e) L.ugid[tid * kUCap + e] = static_cast<int>(v.sorted_gid[L.ugid[tid * kUCap + e]]);
   }
-
-  // Fallback: wave w owns pixels [64 w, 64 w + 64), kPG at a time, lanes
-  // across D, every selected row of the kPG pixels requested from global
-  // memory before any is accumulated.
-  constexpr int kPG = 4;
+  __syncthreads();
   const int dim4 = dim >> 2;
   for (int p0 = wave * 64; p0 < wave * 64 + 64; p0 += kPG) {
+    const int nu = L.unum[p0 / kPG];
+    if (nu >= 0) {
+      for (int c = lane; c < dim4; c += 64) {
+        float4 acc[kPG];
+#pragma unroll
+        for (int q = 0; q < kPG; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int* ug = &L.ugid[(p0 / kPG) * kUCap];
+        const float4* uw = &L.uw[(p0 / kPG) * kUCap];
+        for (int e0 = 0; e0 < nu; e0 += 4) {
+          // four distinct rows requested together (a repeat of the first
+          // with zero weights pads the last step)
+          float4 f[4], w[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const bool ok = e0 + e < nu;
+            f[e] = load_feat4<DT>(v.feats, v.scale, ug[ok ? e0 + e : e0], dim, 4 * c);
+            w[e] = ok ? uw[e0 + e] : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float ws[kPG] = {w[e].x, w[e].y, w[e].z, w[e].w};
+#pragma unroll
+            for (int q = 0; q < kPG; ++q) {
+              acc[q].x += ws[q] * f[e].x;
+              acc[q].y += ws[q] * f[e].y;
+              acc[q].z += ws[q] * f[e].z;
+              acc[q].w += ws[q] * f[e].w;
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kPG; ++q) {
+          const int p = p0 + q;
+          if (L.ns[p] < 0) continue;  // outside the image
+          const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
+          float4* dst = reinterpret_cast<float4*>(v.out + (static_cast<int64_t>(gy) * W + gx) * dim);
+          const float inv = L.inv[p];
+          store_stream(dst + c, make_float4(acc[q].x * inv, acc[q].y * inv, acc[q].z * inv, acc[q].w * inv));
+        }
+      }
+      continue;
+    }
+    // more distinct selections than kUCap: pixel by pixel
     int n[kPG];
     int nmax = 0, safe = 0;
 #pragma unroll
@@ -210,7 +230,7 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
       n[q] = L.ns[p0 + q];
       if (n[q] > nmax) {
         nmax = n[q];
-        safe = static_cast<int>(v.sorted_gid[lo + s_sel_gid[(p0 + q) * K]]);
+        safe = static_cast<int>(v.sorted_gid[s_sel_pos[(p0 + q) * KP]]);
       }
     }
     for (int c = lane; c < dim4; c += 64) {
@@ -223,8 +243,8 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
 #pragma unroll
         for (int q = 0; q < kPG; ++q) {
           const bool ok = j < n[q];
-          const int g = ok ? static_cast<int>(v.sorted_gid[lo + s_sel_gid[(p0 + q) * K + j]]) : safe;
-          w[q] = ok ? s_sel_w[(p0 + q) * K + j] : 0.f;
+          const int g = ok ? static_cast<int>(v.sorted_gid[s_sel_pos[(p0 + q) * KP + j]]) : safe;
+          w[q] = ok ? s_sel_w[(p0 + q) * KP + j] : 0.f;
           f[q] = load_feat4<DT>(v.feats, v.scale, g, dim, 4 * c);
         }
 #pragma unroll
@@ -255,8 +275,8 @@ render_quantile_kernel(ViewArgs v, int n_tiles, qr_params prm, int K, int dim,
                        int32_t* __restrict__ sel_gid_out, float* __restrict__ sel_w_out) {
   extern __shared__ unsigned char dyn_lds[];
   __shared__ QuantileLds L;
-  int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);                 // [256][K]
-  float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * K;  // [256][K]
+  int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);                            // [256][KP]
+  float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);  // [256][KP]
   quantile_tile<DT>(v, xcd_remap(blockIdx.x, n_tiles), K, dim, prm, L, s_sel_gid, s_sel_w,
                     sel_gid_out, sel_w_out);
 }
@@ -273,7 +293,7 @@ render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t
   __shared__ QuantileLds L;
   __shared__ uint32_t s_item;
   int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);
-  float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * K;
+  float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
     __syncthreads();
@@ -313,7 +333,7 @@ extern "C" int qr_render_quantile(void* stream, int32_t width, int32_t height,
   const int tiles_y = static_cast<int>(ceil_div(height, kTile));
   const int n_tiles = tiles_x * tiles_y;
   (void)tiles_x;
-  const size_t lds = static_cast<size_t>(kTilePix) * K * (sizeof(int) + sizeof(float));
+  const size_t lds = static_cast<size_t>(kTilePix) * ((K + 3) & ~3) * (sizeof(int) + sizeof(float));
   hipStream_t s = as_stream(stream);
   const ViewArgs v{width, height, tile_offsets, sorted_gid, reinterpret_cast<const float2*>(means2d),
                    reinterpret_cast<const float4*>(conic_opacity), features, feature_scale, out, T_q,
@@ -356,7 +376,7 @@ extern "C" int qr_render_quantile_batched(void* stream, int32_t n_views, const q
   hipStream_t s = as_stream(stream);
   auto* counter = static_cast<uint32_t*>(workspace);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
-  const size_t lds = static_cast<size_t>(kTilePix) * K * (sizeof(int) + sizeof(float));
+  const size_t lds = static_cast<size_t>(kTilePix) * ((K + 3) & ~3) * (sizeof(int) + sizeof(float));
 #define QR_LAUNCH(DT)                                                                             \
   hipLaunchKernelGGL(render_quantile_batched_kernel<DT>, dim3(n_workgroups), dim3(kTilePix), lds, \
                      s, views, schedule, n_items, counter, *prm, K, dim)
