@@ -81,10 +81,10 @@ def _proj64(proj):
                 opacity=np.asarray(proj["opacity"], np.float64))
 
 
-def _pixels_of_tiles(width, height, tile):
+def _pixels_of_tiles(width, height, tile, tiles=None):
     tiles_x = (width + tile - 1) // tile
     tiles_y = (height + tile - 1) // tile
-    for t in range(tiles_x * tiles_y):
+    for t in (range(tiles_x * tiles_y) if tiles is None else tiles):
         ty, tx = divmod(t, tiles_x)
         for py in range(ty * tile, min((ty + 1) * tile, height)):
             for px in range(tx * tile, min((tx + 1) * tile, width)):
@@ -92,12 +92,14 @@ def _pixels_of_tiles(width, height, tile):
 
 
 def dense_backward(proj, sorted_gid, tile_offsets, features, width, height, grad_out,
-                   params: RenderParams = RenderParams()):
+                   params: RenderParams = RenderParams(), tiles=None):
+    """Gradients of the dense blend; with ``tiles`` only those tiles' pixels
+    contribute (as if grad_out were zero elsewhere)."""
     proj = _proj64(proj)
     F = np.asarray(features, np.float64)
     gout = np.asarray(grad_out, np.float64)
     grads = _new_grads(F.shape[0], F.shape[1])
-    for t, px, py in _pixels_of_tiles(width, height, params.tile):
+    for t, px, py in _pixels_of_tiles(width, height, params.tile, tiles):
         lst = sorted_gid[int(tile_offsets[t]):int(tile_offsets[t + 1])]
         T = 1.0
         blended = []
@@ -121,13 +123,14 @@ def dense_backward(proj, sorted_gid, tile_offsets, features, width, height, grad
 
 
 def quantile_backward(proj, sorted_gid, tile_offsets, features, width, height, K, grad_out,
-                      params: RenderParams = RenderParams()):
+                      params: RenderParams = RenderParams(), tiles=None):
+    """Gradients of Quantile Rendering; ``tiles`` as in dense_backward."""
     proj = _proj64(proj)
     F = np.asarray(features, np.float64)
     gout = np.asarray(grad_out, np.float64)
     grads = _new_grads(F.shape[0], F.shape[1])
     thr = np.append(quantile_thresholds(K), 0.0)
-    for t, px, py in _pixels_of_tiles(width, height, params.tile):
+    for t, px, py in _pixels_of_tiles(width, height, params.tile, tiles):
         lst = sorted_gid[int(tile_offsets[t]):int(tile_offsets[t + 1])]
         T, TQ, k = 1.0, 1.0, 0
         sel = []

@@ -173,3 +173,36 @@ def test_autograd_function_cosine_loss(qr):
             orc = oracle.dense_backward(proj, host["gids"], host["offs"], dec, W, H, g)
         gpu = dict(gf=f.grad.cpu().numpy(), gm=m2.grad.cpu().numpy(), gc=co.grad.cpu().numpy())
         _compare(gpu, orc)
+
+
+def test_backward_diff_config_full_size_sampled_tiles(qr):
+    """500k Gaussians, 640x480, 512-D bf16 storage, K = 8: the backward in the
+    benchmark's launch configuration, with dL/d(out) non-zero on sampled tiles
+    only, so that the oracle can evaluate exactly those tiles."""
+    cfg = synth.CONFIGS["diff"]
+    sc = synth.make_room(cfg["n"], cfg["seed"], dim=cfg["dim"])
+    cam = synth.room_poses(cfg["pose_seeds"], cfg["width"], cfg["height"], cfg["fx"])[0]
+    W, H, K = cam.width, cam.height, cfg["K"]
+    pr, bins, feats, scale, host, dec = _setup(qr, sc, cam, "bf16")
+    proj = proj_for_oracle(host["pr"])
+    lens = np.diff(host["offs"])
+    rng = np.random.default_rng(11)
+    tiles = [int(np.argmax(lens))] + [int(t) for t in rng.choice(np.nonzero(lens > 0)[0], 3, replace=False)]
+    fw = oracle.render_quantile(proj, host["gids"], host["offs"], dec, W, H, K, tiles=tiles)
+    mask = np.zeros((H, W), bool)
+    tx = (W + 15) // 16
+    for t in tiles:
+        ty_, tx_ = divmod(t, tx)
+        mask[ty_ * 16:(ty_ + 1) * 16, tx_ * 16:(tx_ + 1) * 16] = True
+    mask &= ~np.isnan(fw["margin"]) & (np.nan_to_num(fw["margin"]) > DECISION_WINDOW)
+    g = np.random.default_rng(12).standard_normal((H, W, sc.dim)) * mask[..., None]
+    n = sc.n
+    gf = torch.zeros(n, sc.dim, device="cuda")
+    gm = torch.zeros(n, 2, device="cuda")
+    gc = torch.zeros(n, 4, device="cuda")
+    qr._lib.qr_render_quantile_backward(W, H, qr.RenderParams().c(), K, bins.tile_offsets, bins.sorted_gid,
+                                        pr.means2d, pr.conic_opacity, feats, scale,
+                                        _t(g.astype(np.float32)), gf, gm, gc)
+    orc = oracle.quantile_backward(proj, host["gids"], host["offs"], dec, W, H, K, g, tiles=tiles)
+    torch.cuda.synchronize()
+    _compare(dict(gf=gf.cpu().numpy(), gm=gm.cpu().numpy(), gc=gc.cpu().numpy()), orc)

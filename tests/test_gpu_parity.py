@@ -376,3 +376,23 @@ def test_hip_graph_replay_matches_eager(qr):
         torch.cuda.synchronize()
         for a, b in zip((outq, outd, tq, ns), ref):
             assert torch.equal(a, b), i
+
+
+def test_render_parity_precision_full_size_sampled_tiles(qr):
+    """1M Gaussians, 1296x968, 512-D bf16 storage, K = 8: full frame on the
+    GPU, oracle on sampled tiles with the decoded features (kernel error),
+    storage error against the float32 features reported."""
+    cfg = synth.CONFIGS["precision"]
+    sc = synth.make_room(cfg["n"], cfg["seed"], dim=cfg["dim"])
+    cam = synth.room_poses(cfg["pose_seeds"][:1], cfg["width"], cfg["height"], cfg["fx"])[0]
+    res = gpu_pipeline(qr, sc, cam, 8, storage="bf16")
+    tiles = _sample_tiles(res, 5, 3)
+    dec = decoded_features(qr, sc, res, "bf16")
+    ors = oracle_renders(res, dec, cam.width, cam.height, 8, tiles=tiles)
+    check_all(res, ors, cam.width, cam.height, tiles=tiles)
+    orig = oracle.render_quantile(proj_for_oracle(res["pr"]), res["gids"], res["offs"], sc.features,
+                                  cam.width, cam.height, 8, tiles=tiles)
+    ev = ~np.isnan(orig["out"][..., 0]) & (orig["n_sel"] > 0)
+    e = pixel_rel_err(res["q"]["out"][ev], orig["out"][ev])
+    print("precision config bf16 storage error: max %.3e mean %.3e" % (e.max(), e.mean()))
+    assert e.max() < 1e-2
