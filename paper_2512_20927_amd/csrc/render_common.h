@@ -41,7 +41,10 @@ __device__ __forceinline__ AlphaEval eval_alpha(float2 mean, float4 co, float px
   r.dy = pyc - mean.y;
   const float cross2 = ((2.f * co.y) * r.dx) * r.dy;  // products only: nothing to contract
   const float q = fmaf(co.x * r.dx, r.dx, fmaf(co.z * r.dy, r.dy, cross2));
-  r.G = expf(-0.5f * q);
+  // G = exp(-q/2) = 2^(-q log2(e) / 2): one hardware v_exp_f32 (about one ulp;
+  // the rounding of the scaled exponent adds |q| 2^-25 relative)
+  constexpr float kNegHalfLog2e = -0.72134752044448170368f;
+  r.G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
   const float raw = co.w * r.G;
   r.clamped = raw >= alpha_max;
   r.alpha = r.clamped ? alpha_max : raw;
