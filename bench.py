@@ -4,14 +4,17 @@ dense alpha blend.
 
 Workload (room scale): 200k Gaussians in a 6 x 6 x 3 m room (70% near floor
 and wall planes), 512-D float32 features, 640 x 480 pinhole camera
-(fx = fy = 577) at 16 seeded poses, K = 8. One step renders all 16 poses,
-each frame = project + bin_sort + render into a preallocated [480, 640, 512]
-float32 map, with the scene already resident in device memory.
+(fx = fy = 577) at 16 seeded poses, K = 8. One step renders all 16 poses:
+the scene is projected into every pose in one launch, all poses are binned
+into one stacked tile grid, and one batched launch renders every (pose,
+tile) item into 16 preallocated [480, 640, 512] float32 maps; the scene and
+features are resident in device memory before timing starts.
 
 Printed: one JSON line with the Quantile Rendering throughput as `value`,
-the dense throughput beside it, the roofline of the render kernel (HBM bytes
-per launch from the method's algorithmic traffic, timed with HIP events on
-the launch stream), and the FP64 CPU reference timed on a sample of tiles.
+the dense throughput beside it, the roofline of the batched render kernel
+(HBM bytes per launch from the method's algorithmic traffic, timed with HIP
+events on the launch stream), and the FP64 CPU reference timed on a sample
+of tiles.
 """
 
 from __future__ import annotations
@@ -42,7 +45,6 @@ def parse():
                     help="seconds of FP64 CPU reference work (0 disables)")
     ap.add_argument("--renders-only", action="store_true",
                     help="profiling aid: skip the CPU reference")
-    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="profiling aid: first run a plain 1 GiB device copy, whose known "
                          "traffic calibrates the FETCH_SIZE / WRITE_SIZE counters")
@@ -55,7 +57,8 @@ def parse():
 
 
 class FrameRunner:
-    """Preallocated buffers and the per-frame launch sequence."""
+    """Preallocated buffers and the per-frame launch sequence of one lane
+    (frames of a lane run in order on the lane's stream)."""
 
     def __init__(self, qr, L, scene_t, cams, K, capacity, dim, feats=None, scale=None):
         import torch
@@ -92,8 +95,9 @@ class FrameRunner:
 
 
 def timed(runner, which, steps, warmup, n_views):
-    """Runs `steps` steps of n_views frames; HIP events bracket each render
-    launch on the launch stream. Returns (seconds, mean render-kernel ms)."""
+    """Runs `steps` steps of n_views frames on one stream; HIP events bracket
+    each render launch on the launch stream. Returns (seconds, mean
+    render-kernel ms)."""
     import torch
     render = runner.render_q if which == "q" else runner.render_d
     for _ in range(warmup):
@@ -117,29 +121,112 @@ def timed(runner, which, steps, warmup, n_views):
     return dt, kms
 
 
-def timed_graph(runner, which, steps, warmup, n_views):
-    """Captures the launches of one step (n_views frames) in a HIP graph and
-    times `steps` replays. Returns seconds."""
+class BatchState:
+    """One step's worth of device state for the batched path: the projection
+    of the scene into every pose (one launch), the binning of all poses into
+    one stacked tile grid (one launch sequence), and the device view table of
+    the batched Q-Render launch over all (pose, tile) items."""
+
+    def __init__(self, qr, L, scene_t, cams, W, H, capacity, outs, aux_f, aux_i, K, dim):
+        import torch
+        from paper_2512_20927_amd.batched import BatchedQuantile
+        n = scene_t["means"].shape[0]
+        self.L, self.s, self.W, self.H = L, scene_t, W, H
+        self.cams_c = L.make_cameras(cams)
+        self.prm = qr.RenderParams().c()
+        self.pv = qr.render.alloc_projected(len(cams) * n)
+        self.vb = qr.ViewsBinner(len(cams), n, W, H, capacity)
+        self.outs, self.aux_f, self.aux_i = outs, aux_f, aux_i
+        self.per_view = [self.vb.view(self.pv, v) for v in range(len(cams))]
+        views = [dict(tile_offsets=b.tile_offsets, sorted_gid=b.sorted_gid, means2d=pr.means2d,
+                      conic_opacity=pr.conic_opacity, features=scene_t["feats"], feature_scale=None,
+                      out=outs[v], T_q=aux_f[v], n_sel=aux_i[v], width=W, height=H)
+                 for v, (pr, b) in enumerate(self.per_view)]
+        self.bq = BatchedQuantile(views, K, dim, L.QR_F32, self.prm)
+        self.front_done = torch.cuda.Event()
+        self.render_done = torch.cuda.Event()
+
+    def front(self):
+        s, pv = self.s, self.pv
+        self.L.qr_project_views(s["means"], s["scales"], s["quats"], s["opacity"], self.cams_c,
+                                self.prm, pv.means2d, pv.conic_opacity, pv.depth, pv.tile_rect,
+                                pv.tiles_touched)
+        self.vb(pv)
+
+    def render_dense(self):
+        for v, (pr, b) in enumerate(self.per_view):
+            self.L.qr_render_dense(self.W, self.H, self.prm, b.tile_offsets, b.sorted_gid, pr.means2d,
+                                   pr.conic_opacity, self.s["feats"], None, self.outs[v],
+                                   self.aux_f[v], self.aux_i[v])
+
+
+def timed_batched(states, steps, warmup, schedule, wg_per_cu, overlap=True):
+    """`steps` steps of (front, batched render). With overlap, a software
+    pipeline: the front of step i+1 runs on a side stream while step i's
+    render runs on the main stream (the two BatchStates alternate); the timed
+    region holds exactly `steps` fronts and `steps` renders either way.
+    Returns (seconds, mean batched-render ms from HIP events on the render
+    stream)."""
     import torch
-    render = runner.render_q if which == "q" else runner.render_d
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        for v in range(n_views):
-            render(runner.front(v))
-    torch.cuda.current_stream().wait_stream(side)
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        for v in range(n_views):
-            render(runner.front(v))
-    for _ in range(warmup):
-        g.replay()
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream() if overlap else main
+
+    def run(k, evs=None):
+        with torch.cuda.stream(side):
+            side.wait_event(states[0].render_done)
+            states[0].front()
+            states[0].front_done.record(side)
+        for i in range(k):
+            X, Y = states[i % 2], states[(i + 1) % 2]
+            main.wait_event(X.front_done)
+            if evs is not None:
+                evs[i][0].record(main)
+            X.bq.render(schedule, wg_per_cu)
+            if evs is not None:
+                evs[i][1].record(main)
+            X.render_done.record(main)
+            if i + 1 < k:
+                with torch.cuda.stream(side):
+                    side.wait_event(Y.render_done)
+                    Y.front()
+                    Y.front_done.record(side)
+
+    run(max(warmup, 1))
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    run(steps, evs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def timed_dense(state, steps, warmup):
+    """`steps` steps of (front, per-pose dense renders) on one stream."""
+    import torch
+    for _ in range(max(warmup, 1)):
+        state.front()
+        state.render_dense()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        g.replay()
+        state.front()
+        state.render_dense()
     torch.cuda.synchronize()
     return time.perf_counter() - t0
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE passes, calibrated by a 1 GiB copy), or None when
+    there is none or the kernel's sources changed since it was taken."""
+    from paper_2512_20927_amd import profile_summary as ps
+    name = kernel.split("<")[0].replace("_kernel", "")
+    info = ps.read_summary(os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (name, workload)))
+    if not info or info.get("source_sha256") != ps.source_hash("render_quantile"):
+        return None
+    return int(info["traffic_bytes_per_launch"])
 
 
 def cpu_reference(sc, cam, K, budget_s, gpu_out=None, gpu_bins=None):
@@ -217,6 +304,7 @@ def run_room(args):
         del src, dst
     import paper_2512_20927_amd as qr
     from paper_2512_20927_amd import _lib as L
+    from paper_2512_20927_amd.batched import autotune
     import synth
 
     cfg = synth.CONFIGS["room"]
@@ -228,47 +316,61 @@ def run_room(args):
     s = dict(means=t(sc.means), scales=t(sc.scales), quats=t(sc.quats), opacity=t(sc.opacity),
              feats=t(sc.features))
     W, H, D = cfg["width"], cfg["height"], cfg["dim"]
+    n_views = len(cams)
 
-    # per-pose pair counts (setup: a synchronising count), one shared capacity
-    pairs = []
-    for c in cams:
-        pr = qr.project(s["means"], s["scales"], s["quats"], s["opacity"], c)
-        pairs.append(qr.count_pairs(pr))
-    capacity = int(max(pairs) * 1.05) + 1024
-    runner = FrameRunner(qr, L, s, cams, K, capacity, D)
+    # pair counts of all poses (setup: a synchronising count), one capacity
+    pv = qr.project_views(s["means"], s["scales"], s["quats"], s["opacity"], cams)
+    pairs_total = qr.count_pairs(pv)
+    capacity = int(pairs_total * 1.05) + 1024
+    del pv
+
+    # one output map per pose, two alternating batch states
+    outs = [torch.empty(H, W, D, device="cuda") for _ in range(n_views)]
+    aux_f = [torch.empty(H, W, device="cuda") for _ in range(n_views)]
+    aux_i = [torch.empty(H, W, dtype=torch.int32, device="cuda") for _ in range(n_views)]
+    states = [BatchState(qr, L, s, cams, W, H, capacity, outs, aux_f, aux_i, K, D) for _ in range(2)]
+    for st in states:
+        st.front()
+    torch.cuda.synchronize()
+    assert int(states[0].vb.bins.total_pairs.item()) == pairs_total <= capacity
 
     # per-pose statistics for the algorithmic byte count (untimed)
-    uniq, nsel = [], []
-    for v in range(len(cams)):
-        bins = runner.front(v)
-        r = qr.render_quantile(runner.pr, bins, s["feats"], W, H, K, debug=True)
+    pairs, uniq, nsel = [], [], []
+    for v in range(n_views):
+        pr, b = states[0].per_view[v]
+        offs = b.tile_offsets
+        pairs.append(int(offs[-1].item() - offs[0].item()))
+        r = qr.render_quantile(pr, b, s["feats"], W, H, K, debug=True)
         g = r["sel_gid"]
         uniq.append(int(torch.unique(g[g >= 0]).numel()))
         nsel.append(float(r["n_sel"].float().mean().item()))
-        assert int(bins.total_pairs.item()) <= capacity
+        del r, g
+    tuned, tune_ms = autotune(states[0].bq, wg_per_cu=(0, 3, 8), use_cache=False)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
 
-    n_views = len(cams)
-    dt_q, k_q = timed(runner, "q", args.steps, args.warmup, n_views)
-    dt_d, k_d = timed(runner, "d", args.steps, args.warmup, n_views)
+    dt_seq, k_seq = timed_batched(states, args.steps, args.warmup, tuned["schedule"],
+                                  tuned["wg_per_cu"], overlap=False)
+    dt_ovl, k_ovl = timed_batched(states, args.steps, args.warmup, tuned["schedule"],
+                                  tuned["wg_per_cu"], overlap=True)
+    overlap = dt_ovl < dt_seq
+    dt_b, k_b = (dt_ovl, k_ovl) if overlap else (dt_seq, k_seq)
+    dt_d = timed_dense(states[0], args.steps, args.warmup)
     frames = args.steps * n_views
-    eager = {"quantile": frames / dt_q, "dense": frames / dt_d}
-    graph = None
-    if not args.no_graph:
-        gq = timed_graph(runner, "q", args.steps, args.warmup, n_views)
-        gd = timed_graph(runner, "d", args.steps, args.warmup, n_views)
-        graph = {"quantile": frames / gq, "dense": frames / gd}
-    use_graph = graph is not None and graph["quantile"] > eager["quantile"]
-    q_fps = graph["quantile"] if use_graph else eager["quantile"]
-    d_fps = graph["dense"] if use_graph else eager["dense"]
-    dt_step = (frames / q_fps) / args.steps
+    q_fps = frames / dt_b
+    d_fps = frames / dt_d
 
     n_px = W * H
     n_tiles = ((W + 15) // 16) * ((H + 15) // 16)
     bytes_q = [n_px * (D * 4 + 8) + p * 28 + (n_tiles + 1) * 8 + u * D * 4 for p, u in zip(pairs, uniq)]
-    algo_bytes = float(np.mean(bytes_q))
-    achieved = algo_bytes / (k_q * 1e-3) / 1e9
+    bytes_batch = float(np.sum(bytes_q))
+    # the render kernel's own duration: HIP events of the sequential run
+    # bracket the batched launch alone (in the overlapped run the front of the
+    # next step shares the GPU with it)
+    achieved = bytes_batch / (k_seq * 1e-3) / 1e9
+    kernel = ("render_quantile_batched_grid_kernel<0>" if tuned["wg_per_cu"] == 0
+              else "render_quantile_batched_kernel<0>")
+    traffic = measured_traffic(kernel, "room")
 
     cpu = None
     if args.cpu_budget > 0 and not args.renders_only:
@@ -281,7 +383,7 @@ def run_room(args):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt_step * 1e3, 4),
+        "ms_per_step": round(dt_b / args.steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -290,23 +392,27 @@ def run_room(args):
         "config": {
             "workload": "room: 200k Gaussians, 640x480, fx=fy=577, 512-D float32 features, "
                         "Quantile Rendering K=%d, %d poses per step" % (K, n_views),
-            "frame": "project + bin_sort + render into a preallocated [480,640,512] f32 map",
-            "launch": ("HIP graph of one step's launches, replayed" if use_graph
-                       else "eager, one HIP stream"),
+            "step": "project all poses (one launch), bin all poses into one stacked tile grid, "
+                    "one batched Q-Render launch over all (pose, tile) items into %d preallocated "
+                    "[480,640,512] f32 maps%s" % (n_views, "; the next step's projection and "
+                                                  "binning overlap this step's render" if overlap else ""),
+            "batched_launch": {k: tuned[k] for k in ("schedule", "wg_per_cu")},
         },
-        "eager": {k: round(v, 2) for k, v in eager.items()},
-        "graph": {k: round(v, 2) for k, v in graph.items()} if graph else None,
         "dense_value": round(d_fps, 2),
         "q_over_dense": round(q_fps / d_fps, 3),
-        "render_ms": {"quantile": round(k_q, 4), "dense": round(k_d, 4)},
-        "frame_ms": {"quantile": round(1e3 / q_fps, 4), "dense": round(1e3 / d_fps, 4)},
+        "sequential_value": round(frames / dt_seq, 2),
+        "overlapped_value": round(frames / dt_ovl, 2),
+        "render_ms": {"quantile_batched_launch": round(k_seq, 4),
+                      "quantile_batched_launch_overlapped": round(k_ovl, 4)},
         "workload_stats": {"pairs_mean": float(np.mean(pairs)), "selected_unique_mean": float(np.mean(uniq)),
                            "n_sel_mean": float(np.mean(nsel))},
-        "roofline": {"bound": "hbm", "kernel": "render_quantile_kernel<F32>",
+        "roofline": {"bound": "hbm", "kernel": kernel,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_launch": round(algo_bytes)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "bytes_per_launch": round(bytes_batch), "frames_per_launch": n_views},
         "cpu_baseline": cpu,
+        "autotune_ms": {k: round(v, 3) for k, v in tune_ms.items()},
         "setup_s": round(t_setup, 1),
     }
     print(json.dumps(rec))

@@ -140,6 +140,23 @@ int qr_project(void* stream, int64_t n,
                int32_t* tile_rect, uint32_t* tiles_touched);
 
 /*
+ * qr_project_views - qr_project for a batch of n_views cameras of one image
+ * size (Sec. 3, as above), in one launch per 32 cameras: record v*N + i of
+ * every output is Gaussian i seen from cams[v], bit-identical to what
+ * qr_project writes for that camera. cams: HOST array of n_views cameras
+ * (copied into the launch arguments; the call keeps no pointer). Outputs are
+ * device arrays of n_views*N records laid out as for qr_project.
+ * Errors: QR_ERR_INVALID_ARG for n < 0, n_views <= 0, a camera with another
+ * image size or a bad focal length, null pointers; QR_ERR_UNSUPPORTED for
+ * n_views*N >= 2^40.
+ */
+int qr_project_views(void* stream, int64_t n,
+                     const float* means3d, const float* scales, const float* quats,
+                     const float* opacity, int32_t n_views, const qr_camera* cams,
+                     const qr_params* prm, float* means2d, float* conic_opacity,
+                     float* depth, int32_t* tile_rect, uint32_t* tiles_touched);
+
+/*
  * qr_count_pairs - total number of (tile, Gaussian) pairs, sum of
  * tiles_touched. SYNCHRONISES the stream. `workspace` must hold at least
  * 8 bytes (device). Writes *total (host).
@@ -178,6 +195,27 @@ int qr_bin_sort(void* stream, int64_t n, int32_t tiles_x, int32_t tiles_y,
                 void* workspace, size_t workspace_bytes,
                 uint32_t* sorted_gid, uint64_t* sorted_keys,
                 uint32_t* tile_offsets, uint32_t* total_pairs);
+
+/*
+ * qr_bin_sort_views - qr_bin_sort of a batch of views in one launch
+ * sequence: the records are n_views blocks of n_per_view (as written by
+ * qr_project_views), and view v's tiles_x x tiles_y grid takes tile ids
+ * [v*T, (v+1)*T), T = tiles_x*tiles_y. For every tile of every view the list
+ * is exactly the list qr_bin_sort builds for that view alone: VIEW-LOCAL
+ * Gaussian ids in (depth, id) order. tile_offsets u32[n_views*T + 1] indexes
+ * the one shared sorted_gid array (so view v's offsets start at
+ * tile_offsets + v*T); sorted_keys (nullable) hold (stacked tile id << 32) |
+ * depth bits. Workspace: qr_bin_sort_workspace_size(n_views*n_per_view,
+ * tiles_x, n_views*tiles_y, capacity). Capacity semantics as qr_bin_sort.
+ * Errors: as qr_bin_sort; also QR_ERR_INVALID_ARG for n_views <= 0.
+ */
+int qr_bin_sort_views(void* stream, int32_t n_views, int64_t n_per_view,
+                      int32_t tiles_x, int32_t tiles_y,
+                      const int32_t* tile_rect, const uint32_t* tiles_touched,
+                      const float* depth, int64_t capacity,
+                      void* workspace, size_t workspace_bytes,
+                      uint32_t* sorted_gid, uint64_t* sorted_keys,
+                      uint32_t* tile_offsets, uint32_t* total_pairs);
 
 /*
  * qr_render_dense - dense alpha blend of Eq. 1 per pixel:
@@ -224,15 +262,23 @@ int qr_render_quantile(void* stream, int32_t width, int32_t height,
 
 /*
  * qr_render_quantile_batched - Quantile Rendering of many views in one
- * persistent launch: `n_workgroups` workgroups take (view, tile) work items
- * from `schedule` (device u32[n_items], item = (view << QR_BATCH_TILE_BITS) |
- * tile, views < 4096, tiles per view < 2^20) in order through an atomic
- * counter, each rendering one 16x16 tile of one view exactly as
- * qr_render_quantile does. The schedule decides load balance (e.g. the
- * longest tile lists first); every (view, tile) to be rendered must appear
- * once. `views` is a DEVICE array of n_views qr_view records. All views share
- * K, the feature dtype and dim. `workspace` (device, >= 4 bytes) holds the
- * work counter; it is reset by the call.
+ * launch (Algorithm 1, Sec. 4.2, applied to every (view, tile) work item of
+ * `schedule`: device u32[n_items], item = (view << QR_BATCH_TILE_BITS) | tile,
+ * views < 4096, tiles per view < 2^20, n_items < 2^31), each item rendered
+ * exactly as qr_render_quantile renders that tile. `views` is a DEVICE array
+ * of n_views qr_view records; all views share K, the feature dtype and dim.
+ * Every (view, tile) to be rendered must appear once in the schedule.
+ *   n_workgroups == 0: one workgroup per item; items are dealt to the XCDs
+ *     in contiguous runs of the schedule, and workgroups retire as they
+ *     finish (work on other streams can interleave). `workspace` is unused
+ *     and may be NULL.
+ *   n_workgroups > 0: that many persistent workgroups take items in schedule
+ *     order through an atomic counter held in `workspace` (device, >= 4
+ *     bytes), which the call resets; the schedule decides load balance (e.g.
+ *     the longest tile lists first).
+ * Errors: QR_ERR_INVALID_ARG for null pointers, counts out of range or
+ * n_workgroups < 0; QR_ERR_CAPACITY for a missing or short workspace in
+ * persistent mode; QR_ERR_UNSUPPORTED for K, dtype or dim outside the limits.
  */
 int qr_render_quantile_batched(void* stream, int32_t n_views, const qr_view* views,
                                const qr_params* prm, int32_t K, int32_t dtype,

@@ -13,7 +13,9 @@ from .render import (  # noqa: F401
     Projected,
     Bins,
     Binner,
+    ViewsBinner,
     project,
+    project_views,
     count_pairs,
     bin_sort,
     render_quantile,

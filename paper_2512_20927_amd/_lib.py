@@ -28,7 +28,7 @@ EXPORTED = [
     "qr_version", "qr_last_error", "qr_project", "qr_count_pairs",
     "qr_bin_sort_workspace_size", "qr_bin_sort", "qr_render_dense", "qr_render_quantile",
     "qr_render_dense_backward", "qr_render_quantile_backward", "qr_quantize_features",
-    "qr_render_quantile_batched", "qr_batch_schedule",
+    "qr_render_quantile_batched", "qr_batch_schedule", "qr_project_views", "qr_bin_sort_views",
 ]
 QR_BATCH_TILE_BITS = 20
 
@@ -76,6 +76,8 @@ def _load():
         "qr_count_pairs": ([P, i64, P, P, sz, ctypes.POINTER(ctypes.c_uint64)], i32),
         "qr_bin_sort_workspace_size": ([i64, i32, i32, i64, ctypes.POINTER(ctypes.c_size_t)], i32),
         "qr_bin_sort": ([P, i64, i32, i32, P, P, P, i64, P, sz, P, P, P, P], i32),
+        "qr_project_views": ([P, i64, P, P, P, P, i32, cam_p, prm_p, P, P, P, P, P], i32),
+        "qr_bin_sort_views": ([P, i32, i64, i32, i32, P, P, P, i64, P, sz, P, P, P, P], i32),
         "qr_render_dense": ([P, i32, i32, prm_p, P, P, P, P, P, i32, P, i32, P, P, P], i32),
         "qr_render_quantile": ([P, i32, i32, prm_p, i32, P, P, P, P, P, i32, P, i32, P, P, P, P, P], i32),
         "qr_render_dense_backward": ([P, i32, i32, prm_p, P, P, P, P, P, i32, P, i32, P, P, P, P, P], i32),
@@ -198,6 +200,33 @@ def qr_project(means3d, scales, quats, opacity, camera: qr_camera, params: qr_pa
                            _ptr(tiles_touched)))
 
 
+def qr_project_views(means3d, scales, quats, opacity, cameras, params: qr_params,
+                     means2d, conic_opacity, depth, tile_rect, tiles_touched, stream=None):
+    """cameras: a ctypes array of qr_camera (see make_cameras); outputs hold
+    len(cameras) * N records, view-major."""
+    n = means3d.shape[0]
+    nv = len(cameras)
+    for t, k, nm in ((means3d, 3, "means3d"), (scales, 3, "scales"), (quats, 4, "quats"),
+                     (opacity, 1, "opacity")):
+        _need(t, n * k, F32, nm)
+    for t, k, nm in ((means2d, 2, "means2d"), (conic_opacity, 4, "conic_opacity"), (depth, 1, "depth")):
+        _need(t, nv * n * k, F32, nm)
+    _need(tile_rect, 4 * nv * n, I32, "tile_rect")
+    _need(tiles_touched, nv * n, I32, "tiles_touched")
+    _check(_LIB.qr_project_views(_stream(stream), n, _ptr(means3d), _ptr(scales), _ptr(quats),
+                                 _ptr(opacity), nv, cameras, ctypes.byref(params), _ptr(means2d),
+                                 _ptr(conic_opacity), _ptr(depth), _ptr(tile_rect),
+                                 _ptr(tiles_touched)))
+
+
+def make_cameras(cams):
+    """ctypes array of qr_camera from camera-like objects."""
+    arr = (qr_camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = c if isinstance(c, qr_camera) else make_camera(c)
+    return arr
+
+
 def qr_count_pairs(tiles_touched, workspace, stream=None) -> int:
     out = ctypes.c_uint64(0)
     _need(tiles_touched, tiles_touched.shape[0], I32, "tiles_touched")
@@ -226,6 +255,24 @@ def qr_bin_sort(n, tiles_x, tiles_y, tile_rect, tiles_touched, depth, capacity, 
                             _ptr(tiles_touched), _ptr(depth), capacity, _ptr(workspace),
                             workspace.numel() * workspace.element_size(), _ptr(sorted_gid),
                             _ptr(sorted_keys), _ptr(tile_offsets), _ptr(total_pairs)))
+
+
+def qr_bin_sort_views(n_views, n_per_view, tiles_x, tiles_y, tile_rect, tiles_touched, depth,
+                      capacity, workspace, sorted_gid, sorted_keys, tile_offsets, total_pairs,
+                      stream=None):
+    n = n_views * n_per_view
+    _need(tile_rect, 4 * n, I32, "tile_rect")
+    _need(tiles_touched, n, I32, "tiles_touched")
+    _need(depth, n, F32, "depth")
+    _need(sorted_gid, capacity, I32, "sorted_gid")
+    _need(sorted_keys, capacity, (torch.int64,), "sorted_keys")
+    _need(tile_offsets, n_views * tiles_x * tiles_y + 1, I32, "tile_offsets")
+    _need(total_pairs, 1, I32, "total_pairs")
+    _check(_LIB.qr_bin_sort_views(_stream(stream), n_views, n_per_view, tiles_x, tiles_y,
+                                  _ptr(tile_rect), _ptr(tiles_touched), _ptr(depth), capacity,
+                                  _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                  _ptr(sorted_gid), _ptr(sorted_keys), _ptr(tile_offsets),
+                                  _ptr(total_pairs)))
 
 
 def _feat_args(features, feature_scale):
@@ -327,14 +374,18 @@ def qr_quantize_features(features, dtype_code, out, scale=None, stream=None):
 def qr_render_quantile_batched(n_views, views_dev, params, K, dtype_code, dim, schedule, n_workgroups,
                                workspace, stream=None):
     """views_dev: uint8 device tensor holding n_views qr_view records (see
-    pack_views); schedule: int32 device tensor of packed (view, tile) items."""
+    pack_views); schedule: int32 device tensor of packed (view, tile) items;
+    n_workgroups 0 = one workgroup per item (workspace may be None), > 0 =
+    persistent workgroups with the work counter in `workspace`."""
     if views_dev.numel() < n_views * ctypes.sizeof(qr_view):
         raise ValueError("views_dev is smaller than n_views qr_view records")
     _need(schedule, 0, I32, "schedule")
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _check(_LIB.qr_render_quantile_batched(_stream(stream), n_views, _ptr(views_dev),
                                            ctypes.byref(params), K, dtype_code, dim,
                                            _ptr(schedule), schedule.numel(), n_workgroups,
-                                           _ptr(workspace), workspace.numel() * workspace.element_size()))
+                                           _ptr(workspace) if workspace is not None else None,
+                                           ws_bytes))
 
 
 def pack_views(views) -> bytes:

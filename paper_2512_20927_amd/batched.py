@@ -1,11 +1,13 @@
-"""Batched multi-view Quantile Rendering in one persistent launch, and the
-autotuner that picks its tile schedule.
+"""Batched multi-view Quantile Rendering in one launch, and the autotuner
+that picks its launch shape.
 
 A batch is any list of views (each with its own scene, bins and output
 buffer). ``BatchedQuantile`` packs the views' device pointers into a device
-``qr_view`` table once; ``render`` then issues a single persistent launch over
-all (view, tile) items. Two schedules are available: ``natural`` (view-major
-order, fixed) and ``heavy`` (longest tile lists first, built on the device by
+``qr_view`` table once; ``render`` then issues a single launch over all
+(view, tile) items: either one workgroup per item, or a fixed number of
+persistent workgroups per CU taking items through an atomic counter. Two
+schedules (item orders) are available: ``natural`` (view-major order, fixed)
+and ``heavy`` (longest tile lists first, built on the device by
 ``qr_batch_schedule`` from the current bins, so no host round trip). The
 autotuner times the candidates (schedule x workgroups per CU) with HIP events
 and caches the winner as JSON keyed by device, shapes and K.
@@ -58,11 +60,13 @@ class BatchedQuantile:
             return self.heavy
         raise ValueError(kind)
 
-    def render(self, kind: str = "heavy", wg_per_cu: int = 4):
+    def render(self, kind: str = "natural", wg_per_cu: int = 0):
+        """wg_per_cu 0: one workgroup per (view, tile) item; > 0: that many
+        persistent workgroups per CU taking items through a work counter."""
         sched = self.schedule(kind)
         L.qr_render_quantile_batched(self.n_views, self.views_dev, self.params, self.K,
                                      self.dtype_code, self.dim, sched, self.n_cu * wg_per_cu,
-                                     self.counter)
+                                     self.counter if wg_per_cu > 0 else None)
 
     def key(self) -> str:
         shapes = sorted({(v["width"], v["height"]) for v in self._views})
@@ -75,10 +79,11 @@ def default_cache_path() -> str:
                           os.path.join(os.path.expanduser("~"), ".cache", "qrender", "autotune.json"))
 
 
-def autotune(bq: BatchedQuantile, wg_per_cu=(2, 4, 6, 8), schedules=SCHEDULES, reps: int = 3,
+def autotune(bq: BatchedQuantile, wg_per_cu=(0, 2, 4, 8), schedules=SCHEDULES, reps: int = 3,
              cache_path: str | None = None, use_cache: bool = True):
-    """Times every (schedule, workgroups per CU) candidate and returns
-    (best_config, timings_ms). The best is cached under bq.key()."""
+    """Times every (schedule, workgroups per CU) candidate (0 workgroups per
+    CU = one workgroup per item) and returns (best_config, timings_ms). The
+    best is cached under bq.key()."""
     cache_path = cache_path or default_cache_path()
     cache = {}
     if use_cache and os.path.exists(cache_path):

@@ -87,12 +87,50 @@ scan_down_kernel(const uint32_t* __restrict__ in, int64_t n, const uint32_t* __r
   }
 }
 
+// The whole scan in one workgroup, chunk after chunk with a running carry:
+// for short arrays (the per-tile counters of an image) one launch instead of
+// three. out[n] = total (and *total2 if given).
+__global__ void __launch_bounds__(kScanThreads)
+scan_small_kernel(const uint32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ out,
+                  uint32_t* __restrict__ total2) {
+  __shared__ uint32_t lds4[4];
+  uint32_t carry = 0;
+  for (int64_t c = 0; c < n; c += kScanItems) {
+    const int64_t base = c + threadIdx.x * static_cast<int64_t>(kScanPerThread);
+    uint32_t v[kScanPerThread];
+    uint32_t s = 0;
+    for (int j = 0; j < kScanPerThread; ++j) {
+      const int64_t i = base + j;
+      v[j] = i < n ? in[i] : 0u;
+      s += v[j];
+    }
+    uint32_t total;
+    uint32_t run = carry + block_scan_exclusive(s, lds4, &total);
+    for (int j = 0; j < kScanPerThread; ++j) {
+      const int64_t i = base + j;
+      if (i < n) out[i] = run;
+      run += v[j];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    out[n] = carry;
+    if (total2) *total2 = carry;
+  }
+}
+
+constexpr int64_t kSmallScanMax = 16 * kScanItems;  // 32768 entries
+
 static int64_t scan_parts(int64_t n) { return std::max<int64_t>(ceil_div(n, kScanItems), 1); }
 
 // out[0..n) = exclusive scan of in, out[n] = total (and *total2 if given).
 // `part` needs scan_parts(n) + 1 entries; in and out must not overlap.
 static void scan_exclusive(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* part,
                            uint32_t* total2, hipStream_t s) {
+  if (n <= kSmallScanMax) {
+    hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(kScanThreads), 0, s, in, n, out, total2);
+    return;
+  }
   const int64_t nb = scan_parts(n);
   hipLaunchKernelGGL(scan_reduce_kernel, dim3(static_cast<unsigned>(nb)), dim3(kScanThreads), 0, s,
                      in, n, part);
@@ -107,15 +145,19 @@ zero_u32_kernel(uint32_t* __restrict__ a, int64_t n) {
   for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) a[i] = 0u;
 }
 
-// Each wave takes 64 consecutive Gaussians and visits them one after the
-// other; the covered tiles of the current Gaussian are spread over the 64
-// lanes, so a Gaussian that covers a thousand tiles costs sixteen lane-rounds
-// instead of a thousand serial iterations of one thread, and no per-pair
-// index (and no scan of per-Gaussian pair counts) is needed.
+// Each wave takes 64 consecutive projected records and visits them one
+// after the other; the covered tiles of the current record are spread over
+// the 64 lanes, so a Gaussian that covers a thousand tiles costs sixteen
+// lane-rounds instead of a thousand serial iterations of one thread, and no
+// per-pair index (and no scan of per-record pair counts) is needed.
+// Records come in views of n_per_view (record i is Gaussian i % n_per_view
+// seen from view i / n_per_view); view v's tile grid is stacked below view
+// v-1's (tile rows v*tiles_y ..), and the key carries the view-local id.
 template <bool kScatter>
 __global__ void __launch_bounds__(256)
-tile_pairs_kernel(int64_t n, const int4* __restrict__ rect, const uint32_t* __restrict__ touched,
-                  const float* __restrict__ depth, int tiles_x, uint32_t* __restrict__ cnt,
+tile_pairs_kernel(int64_t n, int64_t n_per_view, const int4* __restrict__ rect,
+                  const uint32_t* __restrict__ touched, const float* __restrict__ depth,
+                  int tiles_x, int tiles_y, uint32_t* __restrict__ cnt,
                   const uint32_t* __restrict__ offsets, int64_t capacity,
                   unsigned long long* __restrict__ bucket) {
   const int lane = threadIdx.x & 63;
@@ -124,11 +166,16 @@ tile_pairs_kernel(int64_t n, const int4* __restrict__ rect, const uint32_t* __re
   uint32_t my_cnt = 0;
   int4 my_r = make_int4(0, 0, 0, 0);
   uint32_t my_d = 0;
+  int my_row0 = 0;       // first stacked tile row of this record's footprint
+  uint32_t my_local = 0;  // view-local Gaussian id
   if (mine < n) {
     my_cnt = touched[mine];
     if (my_cnt) {
       my_r = rect[mine];
       if (kScatter) my_d = __float_as_uint(depth[mine]);
+      const int64_t view = mine / n_per_view;
+      my_local = static_cast<uint32_t>(mine - view * n_per_view);
+      my_row0 = static_cast<int>(view) * tiles_y + my_r.y;
     }
   }
   unsigned long long todo = __ballot(my_cnt != 0);
@@ -136,13 +183,14 @@ tile_pairs_kernel(int64_t n, const int4* __restrict__ rect, const uint32_t* __re
     const int j = __ffsll(static_cast<long long>(todo)) - 1;
     todo &= todo - 1;
     const uint32_t c = __shfl(my_cnt, j, 64);
-    const int rx = __shfl(my_r.x, j, 64), ry = __shfl(my_r.y, j, 64), rz = __shfl(my_r.z, j, 64);
+    const int rx = __shfl(my_r.x, j, 64), rz = __shfl(my_r.z, j, 64);
+    const int row0 = __shfl(my_row0, j, 64);
     const int w = rz - rx;
     const unsigned long long key = kScatter
-        ? ((static_cast<unsigned long long>(__shfl(my_d, j, 64)) << 32) | static_cast<uint32_t>(base + j))
+        ? ((static_cast<unsigned long long>(__shfl(my_d, j, 64)) << 32) | __shfl(my_local, j, 64))
         : 0ull;
     for (uint32_t k = lane; k < c; k += 64) {
-      const int t = (ry + static_cast<int>(k) / w) * tiles_x + rx + static_cast<int>(k) % w;
+      const int t = (row0 + static_cast<int>(k) / w) * tiles_x + rx + static_cast<int>(k) % w;
       if (kScatter) {
         const int64_t slot = static_cast<int64_t>(offsets[t]) + atomicAdd(&cnt[t], 1u);
         if (slot < capacity) bucket[slot] = key;
@@ -302,25 +350,28 @@ extern "C" int qr_bin_sort_workspace_size(int64_t n, int32_t tiles_x, int32_t ti
   return QR_OK;
 }
 
-extern "C" int qr_bin_sort(void* stream, int64_t n, int32_t tiles_x, int32_t tiles_y,
-                           const int32_t* tile_rect, const uint32_t* tiles_touched,
-                           const float* depth, int64_t capacity, void* workspace,
-                           size_t workspace_bytes, uint32_t* sorted_gid, uint64_t* sorted_keys,
-                           uint32_t* tile_offsets, uint32_t* total_pairs) {
-  if (n < 0 || capacity < 0) return fail(QR_ERR_INVALID_ARG, "qr_bin_sort: negative size");
-  if (tiles_x <= 0 || tiles_y <= 0) return fail(QR_ERR_INVALID_ARG, "qr_bin_sort: bad tile grid");
-  const int64_t n_tiles = static_cast<int64_t>(tiles_x) * tiles_y;
-  if (n_tiles >= (1ll << 31)) return fail(QR_ERR_UNSUPPORTED, "qr_bin_sort: too many tiles");
-  if (n >= (1ll << 32) || capacity >= (1ll << 32) - 1)
-    return fail(QR_ERR_UNSUPPORTED, "qr_bin_sort: n and capacity must be below 2^32 - 1");
+// Bins the records of n_views views (n_per_view each) into the stacked tile
+// grid of all views: one launch sequence for the whole batch.
+static int bin_sort_impl(const char* name, void* stream, int64_t n_views, int64_t n_per_view,
+                         int32_t tiles_x, int32_t tiles_y, const int32_t* tile_rect,
+                         const uint32_t* tiles_touched, const float* depth, int64_t capacity,
+                         void* workspace, size_t workspace_bytes, uint32_t* sorted_gid,
+                         uint64_t* sorted_keys, uint32_t* tile_offsets, uint32_t* total_pairs) {
+  if (n_views <= 0 || n_per_view < 0 || capacity < 0) return fail(QR_ERR_INVALID_ARG, "%s: negative size", name);
+  if (tiles_x <= 0 || tiles_y <= 0) return fail(QR_ERR_INVALID_ARG, "%s: bad tile grid", name);
+  const int64_t n_tiles = static_cast<int64_t>(tiles_x) * tiles_y * n_views;
+  if (n_tiles >= (1ll << 31)) return fail(QR_ERR_UNSUPPORTED, "%s: too many tiles", name);
+  const int64_t n = n_views * n_per_view;
+  if (n_per_view >= (1ll << 32) || n >= (1ll << 40) || capacity >= (1ll << 32) - 1)
+    return fail(QR_ERR_UNSUPPORTED, "%s: n and capacity must be below 2^32 - 1", name);
   if (!tile_offsets || !total_pairs || !workspace)
-    return fail(QR_ERR_INVALID_ARG, "qr_bin_sort: null output or workspace");
+    return fail(QR_ERR_INVALID_ARG, "%s: null output or workspace", name);
   if (n > 0 && (!tile_rect || !tiles_touched || !depth))
-    return fail(QR_ERR_INVALID_ARG, "qr_bin_sort: null input pointer");
-  if (capacity > 0 && !sorted_gid) return fail(QR_ERR_INVALID_ARG, "qr_bin_sort: null sorted_gid");
+    return fail(QR_ERR_INVALID_ARG, "%s: null input pointer", name);
+  if (capacity > 0 && !sorted_gid) return fail(QR_ERR_INVALID_ARG, "%s: null sorted_gid", name);
   const Layout L = layout(n_tiles, capacity);
   if (workspace_bytes < L.bytes)
-    return fail(QR_ERR_CAPACITY, "qr_bin_sort: workspace needs %zu bytes, got %zu", L.bytes,
+    return fail(QR_ERR_CAPACITY, "%s: workspace needs %zu bytes, got %zu", name, L.bytes,
                 workspace_bytes);
 
   hipStream_t s = as_stream(stream);
@@ -336,18 +387,42 @@ extern "C" int qr_bin_sort(void* stream, int64_t n, int32_t tiles_x, int32_t til
   hipLaunchKernelGGL(zero_u32_kernel, dim3(static_cast<unsigned>(std::min<int64_t>(ceil_div(zero_n, 256), 1024))),
                      dim3(256), 0, s, cnt, zero_n);
   const unsigned gblocks = static_cast<unsigned>(std::max<int64_t>(ceil_div(n, 256), 1));
+  const int64_t npv = std::max<int64_t>(n_per_view, 1);
   if (n > 0)
-    hipLaunchKernelGGL(tile_pairs_kernel<false>, dim3(gblocks), dim3(256), 0, s, n,
-                       reinterpret_cast<const int4*>(tile_rect), tiles_touched, depth, tiles_x, cnt,
-                       nullptr, capacity, nullptr);
+    hipLaunchKernelGGL(tile_pairs_kernel<false>, dim3(gblocks), dim3(256), 0, s, n, npv,
+                       reinterpret_cast<const int4*>(tile_rect), tiles_touched, depth, tiles_x,
+                       tiles_y, cnt, nullptr, capacity, nullptr);
   scan_exclusive(cnt, tile_offsets, n_tiles, part, total_pairs, s);
   if (n > 0 && capacity > 0)
-    hipLaunchKernelGGL(tile_pairs_kernel<true>, dim3(gblocks), dim3(256), 0, s, n,
+    hipLaunchKernelGGL(tile_pairs_kernel<true>, dim3(gblocks), dim3(256), 0, s, n, npv,
                        reinterpret_cast<const int4*>(tile_rect), tiles_touched, depth, tiles_x,
-                       cursor, tile_offsets, capacity, bucket);
+                       tiles_y, cursor, tile_offsets, capacity, bucket);
   if (capacity > 0)
     hipLaunchKernelGGL(tile_sort_kernel, dim3(static_cast<unsigned>(n_tiles)), dim3(256), 0, s,
-                       static_cast<int>(n_tiles), tile_offsets, capacity, bits_for(n), bucket,
+                       static_cast<int>(n_tiles), tile_offsets, capacity, bits_for(n_per_view), bucket,
                        scratch, sorted_gid, reinterpret_cast<unsigned long long*>(sorted_keys));
-  return check_launch("qr_bin_sort");
+  return check_launch(name);
+}
+
+extern "C" int qr_bin_sort(void* stream, int64_t n, int32_t tiles_x, int32_t tiles_y,
+                           const int32_t* tile_rect, const uint32_t* tiles_touched,
+                           const float* depth, int64_t capacity, void* workspace,
+                           size_t workspace_bytes, uint32_t* sorted_gid, uint64_t* sorted_keys,
+                           uint32_t* tile_offsets, uint32_t* total_pairs) {
+  if (n < 0) return fail(QR_ERR_INVALID_ARG, "qr_bin_sort: negative size");
+  if (n >= (1ll << 32)) return fail(QR_ERR_UNSUPPORTED, "qr_bin_sort: n and capacity must be below 2^32 - 1");
+  return bin_sort_impl("qr_bin_sort", stream, 1, n, tiles_x, tiles_y, tile_rect, tiles_touched,
+                       depth, capacity, workspace, workspace_bytes, sorted_gid, sorted_keys,
+                       tile_offsets, total_pairs);
+}
+
+extern "C" int qr_bin_sort_views(void* stream, int32_t n_views, int64_t n_per_view,
+                                 int32_t tiles_x, int32_t tiles_y, const int32_t* tile_rect,
+                                 const uint32_t* tiles_touched, const float* depth,
+                                 int64_t capacity, void* workspace, size_t workspace_bytes,
+                                 uint32_t* sorted_gid, uint64_t* sorted_keys,
+                                 uint32_t* tile_offsets, uint32_t* total_pairs) {
+  return bin_sort_impl("qr_bin_sort_views", stream, n_views, n_per_view, tiles_x, tiles_y,
+                       tile_rect, tiles_touched, depth, capacity, workspace, workspace_bytes,
+                       sorted_gid, sorted_keys, tile_offsets, total_pairs);
 }

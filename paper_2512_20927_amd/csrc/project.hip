@@ -6,24 +6,25 @@
 // structure-of-arrays columns read with unit stride, the outputs are written
 // as float2 / float4 / int4 records so the renderers fetch one Gaussian with
 // one or two vector loads.
+#include <algorithm>
+
 #include "common.h"
 
 namespace qr {
 
-__global__ void __launch_bounds__(256)
-project_kernel(int64_t n, const float* __restrict__ means3d, const float* __restrict__ scales,
-               const float* __restrict__ quats, const float* __restrict__ opacity,
-               qr_camera cam, qr_params prm, int tiles_x, int tiles_y,
-               float2* __restrict__ means2d, float4* __restrict__ conic_opacity,
-               float* __restrict__ depth, int4* __restrict__ rect,
-               uint32_t* __restrict__ touched) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
-
+// Gaussian i seen from `cam`, written to record o of the outputs.
+__device__ __forceinline__ void project_one(int64_t i, int64_t o, const float* __restrict__ means3d,
+                                            const float* __restrict__ scales,
+                                            const float* __restrict__ quats,
+                                            const float* __restrict__ opacity, const qr_camera& cam,
+                                            const qr_params& prm, float2* __restrict__ means2d,
+                                            float4* __restrict__ conic_opacity,
+                                            float* __restrict__ depth, int4* __restrict__ rect,
+                                            uint32_t* __restrict__ touched) {
   const float mx = means3d[3 * i + 0], my = means3d[3 * i + 1], mz = means3d[3 * i + 2];
   const float sx = scales[3 * i + 0], sy = scales[3 * i + 1], sz = scales[3 * i + 2];
   float qw = quats[4 * i + 0], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
-  const float o = opacity[i];
+  const float op = opacity[i];
 
   // camera space
   const float* R = cam.R_cw;
@@ -31,7 +32,7 @@ project_kernel(int64_t n, const float* __restrict__ means3d, const float* __rest
   const float py = R[3] * mx + R[4] * my + R[5] * mz + cam.t[1];
   const float pz = R[6] * mx + R[7] * my + R[8] * mz + cam.t[2];
 
-  bool ok = pz > cam.z_near && o >= prm.alpha_min;
+  bool ok = pz > cam.z_near && op >= prm.alpha_min;
 
   const float inv_z = 1.0f / pz;
   const float u = cam.fx * px * inv_z + cam.cx;
@@ -72,7 +73,7 @@ project_kernel(int64_t n, const float* __restrict__ means3d, const float* __rest
   const float inv_det = 1.0f / det;
 
   // footprint: bounding box of the ellipse where alpha' >= alpha_min
-  const float r2 = 2.0f * logf(o / prm.alpha_min);
+  const float r2 = 2.0f * logf(op / prm.alpha_min);
   const float hx = sqrtf(fmaxf(r2 * cxx, 0.f));
   const float hy = sqrtf(fmaxf(r2 * cyy, 0.f));
   int4 rc = make_int4(0, 0, 0, 0);
@@ -91,16 +92,61 @@ project_kernel(int64_t n, const float* __restrict__ means3d, const float* __rest
       cnt = static_cast<uint32_t>((rc.z - rc.x) * (rc.w - rc.y));
     }
   }
-  means2d[i] = make_float2(u, v);
-  conic_opacity[i] = make_float4(cyy * inv_det, -cxy * inv_det, cxx * inv_det, o);
-  depth[i] = pz;
-  rect[i] = rc;
-  touched[i] = cnt;
+  means2d[o] = make_float2(u, v);
+  conic_opacity[o] = make_float4(cyy * inv_det, -cxy * inv_det, cxx * inv_det, op);
+  depth[o] = pz;
+  rect[o] = rc;
+  touched[o] = cnt;
+}
+
+// Up to kViewChunk cameras per launch, passed by value; blockIdx.y picks the
+// camera, and view v's records occupy [v n, (v + 1) n) of every output. The
+// single-camera entry point launches the same kernel with one camera, so one
+// view projected alone or in a batch gives bit-identical records.
+constexpr int kViewChunk = 32;
+struct CameraChunk {
+  qr_camera cam[kViewChunk];
+};
+
+__global__ void __launch_bounds__(256)
+project_views_kernel(int64_t n, const float* __restrict__ means3d, const float* __restrict__ scales,
+                     const float* __restrict__ quats, const float* __restrict__ opacity,
+                     CameraChunk cams, int64_t first_view, qr_params prm,
+                     float2* __restrict__ means2d, float4* __restrict__ conic_opacity,
+                     float* __restrict__ depth, int4* __restrict__ rect,
+                     uint32_t* __restrict__ touched) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = (first_view + blockIdx.y) * n + i;
+  project_one(i, o, means3d, scales, quats, opacity, cams.cam[blockIdx.y], prm, means2d,
+              conic_opacity, depth, rect, touched);
 }
 
 }  // namespace qr
 
 using namespace qr;
+
+static int check_camera(const char* name, const qr_camera* cam) {
+  if (cam->width <= 0 || cam->height <= 0)
+    return fail(QR_ERR_INVALID_ARG, "%s: image size must be positive", name);
+  if (!(cam->fx > 0.f) || !(cam->fy > 0.f))
+    return fail(QR_ERR_INVALID_ARG, "%s: focal lengths must be positive", name);
+  return QR_OK;
+}
+
+static int check_project_args(const char* name, int64_t n, const qr_params* prm,
+                              const float* means3d, const float* scales, const float* quats,
+                              const float* opacity, const float* means2d,
+                              const float* conic_opacity, const float* depth,
+                              const int32_t* tile_rect, const uint32_t* tiles_touched) {
+  if (!(prm->alpha_min > 0.f) || !(prm->alpha_max >= prm->alpha_min))
+    return fail(QR_ERR_INVALID_ARG, "%s: need 0 < alpha_min <= alpha_max", name);
+  if (n == 0) return QR_OK;
+  if (!means3d || !scales || !quats || !opacity || !means2d || !conic_opacity || !depth ||
+      !tile_rect || !tiles_touched)
+    return fail(QR_ERR_INVALID_ARG, "%s: null array pointer", name);
+  return QR_OK;
+}
 
 extern "C" int qr_project(void* stream, int64_t n, const float* means3d, const float* scales,
                           const float* quats, const float* opacity, const qr_camera* cam,
@@ -108,24 +154,49 @@ extern "C" int qr_project(void* stream, int64_t n, const float* means3d, const f
                           float* depth, int32_t* tile_rect, uint32_t* tiles_touched) {
   if (n < 0) return fail(QR_ERR_INVALID_ARG, "qr_project: n < 0");
   if (!cam || !prm) return fail(QR_ERR_INVALID_ARG, "qr_project: null camera or params");
-  if (cam->width <= 0 || cam->height <= 0)
-    return fail(QR_ERR_INVALID_ARG, "qr_project: image size must be positive");
-  if (!(cam->fx > 0.f) || !(cam->fy > 0.f))
-    return fail(QR_ERR_INVALID_ARG, "qr_project: focal lengths must be positive");
-  if (!(prm->alpha_min > 0.f) || !(prm->alpha_max >= prm->alpha_min))
-    return fail(QR_ERR_INVALID_ARG, "qr_project: need 0 < alpha_min <= alpha_max");
-  if (n == 0) return QR_OK;
-  if (!means3d || !scales || !quats || !opacity || !means2d || !conic_opacity || !depth ||
-      !tile_rect || !tiles_touched)
-    return fail(QR_ERR_INVALID_ARG, "qr_project: null array pointer");
-  const int tiles_x = static_cast<int>(ceil_div(cam->width, kTile));
-  const int tiles_y = static_cast<int>(ceil_div(cam->height, kTile));
-  const int threads = 256;
-  const int64_t blocks = ceil_div(n, threads);
-  hipLaunchKernelGGL(project_kernel, dim3(static_cast<unsigned>(blocks)), dim3(threads), 0,
-                     as_stream(stream), n, means3d, scales, quats, opacity, *cam, *prm, tiles_x,
-                     tiles_y, reinterpret_cast<float2*>(means2d),
+  int rc = check_camera("qr_project", cam);
+  if (rc == QR_OK)
+    rc = check_project_args("qr_project", n, prm, means3d, scales, quats, opacity, means2d,
+                            conic_opacity, depth, tile_rect, tiles_touched);
+  if (rc != QR_OK || n == 0) return rc;
+  CameraChunk chunk{};
+  chunk.cam[0] = *cam;
+  hipLaunchKernelGGL(project_views_kernel, dim3(static_cast<unsigned>(ceil_div(n, 256)), 1u), dim3(256),
+                     0, as_stream(stream), n, means3d, scales, quats, opacity, chunk, int64_t{0},
+                     *prm, reinterpret_cast<float2*>(means2d),
                      reinterpret_cast<float4*>(conic_opacity), depth,
                      reinterpret_cast<int4*>(tile_rect), tiles_touched);
   return check_launch("qr_project");
+}
+
+extern "C" int qr_project_views(void* stream, int64_t n, const float* means3d, const float* scales,
+                                const float* quats, const float* opacity, int32_t n_views,
+                                const qr_camera* cams, const qr_params* prm, float* means2d,
+                                float* conic_opacity, float* depth, int32_t* tile_rect,
+                                uint32_t* tiles_touched) {
+  if (n < 0 || n_views <= 0) return fail(QR_ERR_INVALID_ARG, "qr_project_views: n < 0 or n_views <= 0");
+  if (!cams || !prm) return fail(QR_ERR_INVALID_ARG, "qr_project_views: null cameras or params");
+  for (int32_t v = 0; v < n_views; ++v) {
+    const int rc = check_camera("qr_project_views", &cams[v]);
+    if (rc != QR_OK) return rc;
+    if (cams[v].width != cams[0].width || cams[v].height != cams[0].height)
+      return fail(QR_ERR_INVALID_ARG, "qr_project_views: camera %d has another image size", v);
+  }
+  if (n * static_cast<int64_t>(n_views) >= (1ll << 40))
+    return fail(QR_ERR_UNSUPPORTED, "qr_project_views: too many records");
+  const int rc = check_project_args("qr_project_views", n, prm, means3d, scales, quats, opacity,
+                                    means2d, conic_opacity, depth, tile_rect, tiles_touched);
+  if (rc != QR_OK || n == 0) return rc;
+  hipStream_t s = as_stream(stream);
+  const unsigned blocks = static_cast<unsigned>(ceil_div(n, 256));
+  for (int32_t v0 = 0; v0 < n_views; v0 += kViewChunk) {
+    const int nv = std::min<int32_t>(kViewChunk, n_views - v0);
+    CameraChunk chunk{};
+    for (int k = 0; k < nv; ++k) chunk.cam[k] = cams[v0 + k];
+    hipLaunchKernelGGL(project_views_kernel, dim3(blocks, static_cast<unsigned>(nv)), dim3(256), 0,
+                       s, n, means3d, scales, quats, opacity, chunk, static_cast<int64_t>(v0), *prm,
+                       reinterpret_cast<float2*>(means2d), reinterpret_cast<float4*>(conic_opacity),
+                       depth, reinterpret_cast<int4*>(tile_rect), tiles_touched);
+  }
+  return check_launch("qr_project_views");
 }

@@ -32,6 +32,12 @@ constexpr int kGroups = kTilePix / kPG;    // 64 pixel groups per tile
 #define QR_UCAP 16
 #endif
 constexpr int kUCap = QR_UCAP;             // distinct selections kept per group
+#ifndef QR_GATHER_ROWS
+#define QR_GATHER_ROWS 4                   // distinct rows requested together in the gather
+#endif
+// Three 45 KB workgroups fill a CU's LDS: registers are bounded to match
+// (three waves per SIMD).
+constexpr int kWavesPerSimd = 3;
 
 struct QuantileLds {
   float2 mean[kTilePix];
@@ -40,8 +46,8 @@ struct QuantileLds {
   float inv[kTilePix];
   int ns[kTilePix];
   int unum[kGroups];                       // distinct entries per group, -1 if over kUCap
-  int ugid[kGroups * kUCap];
-  float4 uw[kGroups * kUCap];              // the group's four pixel weights, x = first pixel
+  int ugid[kGroups * kUCap];               // a group's distinct selections (list positions until converted)
+  float4 uw[kGroups * kUCap];              // their weights for the group's four pixels, x = first pixel
 };
 
 struct ViewArgs {
@@ -57,9 +63,132 @@ struct ViewArgs {
   int32_t* __restrict__ n_sel;
 };
 
+// Orders this wave's LDS writes before its later LDS reads (all lanes).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Gather-blend of one 4-pixel group whose distinct selections are merged:
+// out[p] = (sum_e w_pe f_e) / (1 - T^Q_p). Each lane owns two float4 columns
+// per pass (512 features per pass for the wave); kEB distinct rows are
+// requested for both columns before any is used. Rows past the end repeat
+// the last one with zero weight, so the loads are unconditional.
+template <int DT>
+__device__ __forceinline__ void gather_group_merged(const ViewArgs& v, const QuantileLds& L, int grp,
+                                                    int nu, int tx, int ty, int lane, int dim) {
+  constexpr int kEB = QR_GATHER_ROWS;
+  const int dim4 = dim >> 2;
+  const int p0 = grp * kPG;
+  const int* ug = &L.ugid[grp * kUCap];
+  const float4* uw = &L.uw[grp * kUCap];
+  for (int cb = 0; cb < dim4; cb += 128) {
+    const int c0 = cb + lane, c1 = cb + 64 + lane;
+    const int l0 = min(c0, dim4 - 1), l1 = min(c1, dim4 - 1);  // in-bounds columns to load
+    float4 a0[kPG], a1[kPG];
+#pragma unroll
+    for (int q = 0; q < kPG; ++q) {
+      a0[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      a1[q] = a0[q];
+    }
+    for (int e0 = 0; e0 < nu; e0 += kEB) {
+      float4 f0[kEB], f1[kEB];
+#pragma unroll
+      for (int e = 0; e < kEB; ++e) {
+        const int g = __builtin_amdgcn_readfirstlane(ug[min(e0 + e, nu - 1)]);
+        f0[e] = load_feat4<DT>(v.feats, v.scale, g, dim, 4 * l0);
+        f1[e] = load_feat4<DT>(v.feats, v.scale, g, dim, 4 * l1);
+      }
+#pragma unroll
+      for (int e = 0; e < kEB; ++e) {
+        const float4 w = e0 + e < nu ? uw[e0 + e] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float ws[kPG] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int q = 0; q < kPG; ++q) {
+          a0[q].x += ws[q] * f0[e].x;
+          a0[q].y += ws[q] * f0[e].y;
+          a0[q].z += ws[q] * f0[e].z;
+          a0[q].w += ws[q] * f0[e].w;
+          a1[q].x += ws[q] * f1[e].x;
+          a1[q].y += ws[q] * f1[e].y;
+          a1[q].z += ws[q] * f1[e].z;
+          a1[q].w += ws[q] * f1[e].w;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kPG; ++q) {
+      const int p = p0 + q;
+      if (L.ns[p] < 0) continue;  // outside the image
+      const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
+      float4* dst = reinterpret_cast<float4*>(v.out + (static_cast<int64_t>(gy) * v.W + gx) * dim);
+      const float inv = L.inv[p];
+      if (c0 < dim4) store_stream(dst + c0, make_float4(a0[q].x * inv, a0[q].y * inv, a0[q].z * inv, a0[q].w * inv));
+      if (c1 < dim4) store_stream(dst + c1, make_float4(a1[q].x * inv, a1[q].y * inv, a1[q].z * inv, a1[q].w * inv));
+    }
+  }
+}
+
+// Gather-blend of a group with more than kUCap distinct selections: pixel
+// by pixel, each selection's row loaded for its own pixel.
+template <int DT>
+__device__ __forceinline__ void gather_group_per_pixel(const ViewArgs& v, const QuantileLds& L,
+                                                       const int* __restrict__ s_sel_pos,
+                                                       const float* __restrict__ s_sel_w, int KP,
+                                                       int grp, int tx, int ty, int lane, int dim) {
+  const int dim4 = dim >> 2;
+  const int p0 = grp * kPG;
+  int n[kPG];
+  int nmax = 0, safe = 0;
+#pragma unroll
+  for (int q = 0; q < kPG; ++q) {
+    n[q] = L.ns[p0 + q];
+    if (n[q] > nmax) {
+      nmax = n[q];
+      safe = static_cast<int>(v.sorted_gid[s_sel_pos[(p0 + q) * KP]]);
+    }
+  }
+  for (int c = lane; c < dim4; c += 64) {
+    float4 acc[kPG];
+#pragma unroll
+    for (int q = 0; q < kPG; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int j = 0; j < nmax; ++j) {
+      float4 f[kPG];
+      float w[kPG];
+#pragma unroll
+      for (int q = 0; q < kPG; ++q) {
+        const bool ok = j < n[q];
+        const int g = ok ? static_cast<int>(v.sorted_gid[s_sel_pos[(p0 + q) * KP + j]]) : safe;
+        w[q] = ok ? s_sel_w[(p0 + q) * KP + j] : 0.f;
+        f[q] = load_feat4<DT>(v.feats, v.scale, g, dim, 4 * c);
+      }
+#pragma unroll
+      for (int q = 0; q < kPG; ++q) {
+        acc[q].x += w[q] * f[q].x;
+        acc[q].y += w[q] * f[q].y;
+        acc[q].z += w[q] * f[q].z;
+        acc[q].w += w[q] * f[q].w;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kPG; ++q) {
+      if (n[q] < 0) continue;  // outside the image
+      const int p = p0 + q;
+      const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
+      float4* dst = reinterpret_cast<float4*>(v.out + (static_cast<int64_t>(gy) * v.W + gx) * dim);
+      const float inv = L.inv[p];
+      store_stream(dst + c, make_float4(acc[q].x * inv, acc[q].y * inv, acc[q].z * inv, acc[q].w * inv));
+    }
+  }
+}
+
 // Algorithm 1 for every pixel of one tile, then the gather-blend of the
-// selected rows. Called by all 256 threads of the workgroup; starts and ends
-// with the workgroup synchronised.
+// selected rows. Called by all 256 threads of the workgroup. Workgroup
+// barriers occur only around the staging of record batches; the pixels of
+// wave w are tile rows 4w .. 4w+3, which are exactly the pixels of the
+// gather groups it owns, so everything after the walk is wave-local.
+// Shared LDS (the record batch) is only rewritten after a barrier that every
+// wave reaches once it has finished the previous tile.
 template <int DT>
 __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K, int dim,
                                               const qr_params& prm, QuantileLds& L,
@@ -76,7 +205,8 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
   const bool inside = px < W && py < H;
   const float pxc = px + 0.5f, pyc = py + 0.5f;
 
-  if (tid <= K) L.thr[tid] = quantile_threshold(tid + 1, K);  // thr[k] = t_{k+1}; thr[K] = 0
+  // thr[k] = t_{k+1}; thr[K] = 0 (identical for every tile of a launch)
+  if (tid <= K) L.thr[tid] = quantile_threshold(tid + 1, K);
 
   const int lo = static_cast<int>(v.tile_offsets[tile]);
   const int hi = static_cast<int>(v.tile_offsets[tile + 1]);
@@ -88,6 +218,7 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
   int* s_sel_pos = s_sel_gid;  // selections are kept as tile-list positions
   int* my_pos = s_sel_pos + tid * KP;
   float* my_w = s_sel_w + tid * KP;
+  const float amin = prm.alpha_min, amax = prm.alpha_max;
 
   for (int batch = lo; batch < hi; batch += kTilePix) {
     if (__syncthreads_count(!done) == 0) break;
@@ -96,53 +227,47 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
       const int g = static_cast<int>(v.sorted_gid[idx]);
       L.mean[tid] = v.means2d[g];
       L.co[tid] = v.conic_opacity[g];
+    } else {  // padding record: opacity 0 is below alpha_min on every ray
+      L.mean[tid] = make_float2(0.f, 0.f);
+      L.co[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     __syncthreads();
-    const int cnt = min(kTilePix, hi - batch);
-    for (int j = 0; j < cnt && !done; ++j) {
-      const float alpha = gauss_alpha(L.mean[j], L.co[j], pxc, pyc, prm.alpha_max);
-      if (alpha < prm.alpha_min) continue;  // not on this pixel's ray
-      const float T_test = T * (1.f - alpha);
-      if (T_test < L.thr[k]) {  // crossing: a quantile Gaussian
-        my_pos[ns] = batch + j;
-        my_w[ns] = TQ * alpha;
-        ++ns;
-        TQ = TQ * (1.f - alpha);
-        ++k;
-        while (k < K && T_test < L.thr[k]) ++k;  // thresholds crossed by the same step
-        if (k == K) done = true;
-      }
-      T = T_test;
-    }
-  }
-  if (inside) {
-    const int pix = py * W + px;
-    if (v.T_q) v.T_q[pix] = TQ;
-    if (v.n_sel) v.n_sel[pix] = ns;
-    if (sel_gid_out) {
-      for (int j = 0; j < K; ++j) {
-        sel_gid_out[static_cast<int64_t>(pix) * K + j] =
-            j < ns ? static_cast<int>(v.sorted_gid[my_pos[j]]) : -1;
-        sel_w_out[static_cast<int64_t>(pix) * K + j] = j < ns ? my_w[j] : 0.f;
+    const int cnt4 = (min(kTilePix, hi - batch) + 3) & ~3;
+    for (int j = 0; j < cnt4; j += 4) {
+      if (__all(done)) break;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float alpha = gauss_alpha(L.mean[j + u], L.co[j + u], pxc, pyc, amax);
+        if (done || alpha < amin) continue;  // finished, or not on this pixel's ray
+        const float T_test = T * (1.f - alpha);
+        if (T_test < L.thr[k]) {  // crossing: a quantile Gaussian
+          my_pos[ns] = batch + j + u;
+          my_w[ns] = TQ * alpha;
+          ++ns;
+          TQ = TQ * (1.f - alpha);
+          ++k;
+          while (k < K && T_test < L.thr[k]) ++k;  // thresholds crossed by the same step
+          if (k == K) done = true;
+        }
+        T = T_test;
       }
     }
   }
   L.ns[tid] = inside ? ns : -1;
   L.inv[tid] = ns > 0 ? 1.f / (1.f - TQ) : 0.f;
-  __syncthreads();
+  wave_lds_sync();
 
-  // Phase 2: gather-blend out[p] = sum_j w_pj f_j / (1 - T^Q_p). Pixels
-  // are gathered four at a time (a row segment of the tile), lanes across D.
-  // Adjacent pixels select mostly the same Gaussians, so each group's four
-  // selection lists (ordered by list position) are first merged into its
-  // distinct selections, each carrying the four pixels' weights (0 where a
-  // pixel did not select it): every distinct feature row is then loaded once
-  // per group instead of once per selecting pixel. A group with more than
-  // kUCap distinct selections gathers pixel by pixel.
+  // Phase 2, wave-local: adjacent pixels select mostly the same Gaussians,
+  // so each group's four selection lists (ordered by list position) are
+  // merged into its distinct selections, each carrying the four pixels'
+  // weights (0 where a pixel did not select it), and every distinct row is
+  // loaded once per group. Lane l < 16 merges group 16 w + l.
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  if (tid < kGroups) {
-    const int p0 = tid * kPG;
+  constexpr int kWaveGroups = kGroups / 4;
+  if (lane < kWaveGroups) {
+    const int grp = wave * kWaveGroups + lane;
+    const int p0 = grp * kPG;
     int n[kPG], idx[kPG];
 #pragma unroll
     for (int q = 0; q < kPG; ++q) {
@@ -169,108 +294,41 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
           ++idx[q];
         }
       }
-      L.ugid[tid * kUCap + cnt] = best;  // position for now
-      L.uw[tid * kUCap + cnt] = make_float4(wq[0], wq[1], wq[2], wq[3]);
+      L.ugid[grp * kUCap + cnt] = best;  // position for now
+      L.uw[grp * kUCap + cnt] = make_float4(wq[0], wq[1], wq[2], wq[3]);
       ++cnt;
     }
-    L.unum[tid] = cnt;
+    L.unum[grp] = cnt;
     // positions -> Gaussian ids (independent loads)
-    for (int e = 0; e < cnt; ++e) L.ugid[tid * kUCap + e] = static_cast<int>(v.sorted_gid[L.ugid[tid * kUCap + e]]);
+    for (int e = 0; e < cnt; ++e) L.ugid[grp * kUCap + e] = static_cast<int>(v.sorted_gid[L.ugid[grp * kUCap + e]]);
   }
-  __syncthreads();
-  const int dim4 = dim >> 2;
-  for (int p0 = wave * 64; p0 < wave * 64 + 64; p0 += kPG) {
-    const int nu = L.unum[p0 / kPG];
-    if (nu >= 0) {
-      for (int c = lane; c < dim4; c += 64) {
-        float4 acc[kPG];
-#pragma unroll
-        for (int q = 0; q < kPG; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-        const int* ug = &L.ugid[(p0 / kPG) * kUCap];
-        const float4* uw = &L.uw[(p0 / kPG) * kUCap];
-        for (int e0 = 0; e0 < nu; e0 += 4) {
-          // four distinct rows requested together (a repeat of the first
-          // with zero weights pads the last step)
-          float4 f[4], w[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const bool ok = e0 + e < nu;
-            f[e] = load_feat4<DT>(v.feats, v.scale, ug[ok ? e0 + e : e0], dim, 4 * c);
-            w[e] = ok ? uw[e0 + e] : make_float4(0.f, 0.f, 0.f, 0.f);
-          }
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float ws[kPG] = {w[e].x, w[e].y, w[e].z, w[e].w};
-#pragma unroll
-            for (int q = 0; q < kPG; ++q) {
-              acc[q].x += ws[q] * f[e].x;
-              acc[q].y += ws[q] * f[e].y;
-              acc[q].z += ws[q] * f[e].z;
-              acc[q].w += ws[q] * f[e].w;
-            }
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < kPG; ++q) {
-          const int p = p0 + q;
-          if (L.ns[p] < 0) continue;  // outside the image
-          const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
-          float4* dst = reinterpret_cast<float4*>(v.out + (static_cast<int64_t>(gy) * W + gx) * dim);
-          const float inv = L.inv[p];
-          store_stream(dst + c, make_float4(acc[q].x * inv, acc[q].y * inv, acc[q].z * inv, acc[q].w * inv));
-        }
-      }
-      continue;
-    }
-    // more distinct selections than kUCap: pixel by pixel
-    int n[kPG];
-    int nmax = 0, safe = 0;
-#pragma unroll
-    for (int q = 0; q < kPG; ++q) {
-      n[q] = L.ns[p0 + q];
-      if (n[q] > nmax) {
-        nmax = n[q];
-        safe = static_cast<int>(v.sorted_gid[s_sel_pos[(p0 + q) * KP]]);
-      }
-    }
-    for (int c = lane; c < dim4; c += 64) {
-      float4 acc[kPG];
-#pragma unroll
-      for (int q = 0; q < kPG; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-      for (int j = 0; j < nmax; ++j) {
-        float4 f[kPG];
-        float w[kPG];
-#pragma unroll
-        for (int q = 0; q < kPG; ++q) {
-          const bool ok = j < n[q];
-          const int g = ok ? static_cast<int>(v.sorted_gid[s_sel_pos[(p0 + q) * KP + j]]) : safe;
-          w[q] = ok ? s_sel_w[(p0 + q) * KP + j] : 0.f;
-          f[q] = load_feat4<DT>(v.feats, v.scale, g, dim, 4 * c);
-        }
-#pragma unroll
-        for (int q = 0; q < kPG; ++q) {
-          acc[q].x += w[q] * f[q].x;
-          acc[q].y += w[q] * f[q].y;
-          acc[q].z += w[q] * f[q].z;
-          acc[q].w += w[q] * f[q].w;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kPG; ++q) {
-        if (n[q] < 0) continue;  // outside the image
-        const int p = p0 + q;
-        const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
-        float4* dst = reinterpret_cast<float4*>(v.out + (static_cast<int64_t>(gy) * W + gx) * dim);
-        const float inv = L.inv[p];
-        store_stream(dst + c, make_float4(acc[q].x * inv, acc[q].y * inv, acc[q].z * inv, acc[q].w * inv));
+  wave_lds_sync();
+  for (int gl = 0; gl < kWaveGroups; ++gl) {
+    const int grp = wave * kWaveGroups + gl;
+    const int nu = __builtin_amdgcn_readfirstlane(L.unum[grp]);
+    if (nu >= 0)
+      gather_group_merged<DT>(v, L, grp, nu, tx, ty, lane, dim);
+    else  // more distinct selections than kUCap (rare)
+      gather_group_per_pixel<DT>(v, L, s_sel_pos, s_sel_w, KP, grp, tx, ty, lane, dim);
+  }
+  // Per-pixel outputs last: a load issued after a store waits for it, so no
+  // store precedes the loads of the merge and the gather.
+  if (inside) {
+    const int pix = py * W + px;
+    if (v.T_q) v.T_q[pix] = TQ;
+    if (v.n_sel) v.n_sel[pix] = ns;
+    if (sel_gid_out) {
+      for (int j = 0; j < K; ++j) {
+        sel_gid_out[static_cast<int64_t>(pix) * K + j] =
+            j < ns ? static_cast<int>(v.sorted_gid[my_pos[j]]) : -1;
+        sel_w_out[static_cast<int64_t>(pix) * K + j] = j < ns ? my_w[j] : 0.f;
       }
     }
   }
-  __syncthreads();
 }
 
 template <int DT>
-__global__ void __launch_bounds__(kTilePix)
+__global__ void __launch_bounds__(kTilePix, kWavesPerSimd)
 render_quantile_kernel(ViewArgs v, int n_tiles, qr_params prm, int K, int dim,
                        int32_t* __restrict__ sel_gid_out, float* __restrict__ sel_w_out) {
   extern __shared__ unsigned char dyn_lds[];
@@ -281,33 +339,59 @@ render_quantile_kernel(ViewArgs v, int n_tiles, qr_params prm, int K, int dim,
                     sel_gid_out, sel_w_out);
 }
 
+__device__ __forceinline__ ViewArgs view_args(const qr_view& qv) {
+  return ViewArgs{qv.width, qv.height, qv.tile_offsets, qv.sorted_gid,
+                  reinterpret_cast<const float2*>(qv.means2d),
+                  reinterpret_cast<const float4*>(qv.conic_opacity), qv.features,
+                  qv.feature_scale, qv.out, qv.T_q, qv.n_sel};
+}
+
 // Many views in one persistent launch. Workgroups take (view, tile) items
 // from `schedule` in order through an atomic counter until it is exhausted;
 // every workgroup leaves once the counter passes n_items.
 template <int DT>
-__global__ void __launch_bounds__(kTilePix)
+__global__ void __launch_bounds__(kTilePix, kWavesPerSimd)
 render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t* __restrict__ schedule,
                                int64_t n_items, uint32_t* __restrict__ counter, qr_params prm,
                                int K, int dim) {
   extern __shared__ unsigned char dyn_lds[];
   __shared__ QuantileLds L;
-  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_item[2];
   int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);
-  for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+  // The item slot alternates between two words: a wave that runs ahead into
+  // the next iteration writes the other word, and cannot come back to this
+  // one before every wave has passed the next barrier (and so has read it).
+  for (int it = 0;; it ^= 1) {
+    if (threadIdx.x == 0) s_item[it] = atomicAdd(counter, 1u);
     __syncthreads();
-    const uint32_t item = s_item;
+    // uniform values: view records and tile indices stay in scalar registers
+    const uint32_t item = __builtin_amdgcn_readfirstlane(s_item[it]);
     if (item >= n_items) break;
-    const uint32_t packed = schedule[item];
-    const qr_view& qv = views[packed >> kViewShift];
-    ViewArgs v{qv.width, qv.height, qv.tile_offsets, qv.sorted_gid,
-               reinterpret_cast<const float2*>(qv.means2d),
-               reinterpret_cast<const float4*>(qv.conic_opacity), qv.features,
-               qv.feature_scale, qv.out, qv.T_q, qv.n_sel};
+    const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[item]);
+    const ViewArgs v = view_args(views[packed >> kViewShift]);
     quantile_tile<DT>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
                       nullptr, nullptr);
   }
+}
+
+// Many views in one launch, one workgroup per (view, tile) item. Items are
+// dealt to the XCDs in contiguous runs of the schedule (neighbouring tiles of
+// a view share L2 contents); workgroups retire as they finish, so work on
+// other streams can take their slots.
+template <int DT>
+__global__ void __launch_bounds__(kTilePix, kWavesPerSimd)
+render_quantile_batched_grid_kernel(const qr_view* __restrict__ views,
+                                    const uint32_t* __restrict__ schedule, int n_items,
+                                    qr_params prm, int K, int dim) {
+  extern __shared__ unsigned char dyn_lds[];
+  __shared__ QuantileLds L;
+  int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);
+  float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);
+  const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[xcd_remap(blockIdx.x, n_items)]);
+  const ViewArgs v = view_args(views[packed >> kViewShift]);
+  quantile_tile<DT>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
+                    nullptr, nullptr);
 }
 
 __global__ void reset_counter_kernel(uint32_t* __restrict__ c) { *c = 0u; }
@@ -357,13 +441,13 @@ extern "C" int qr_render_quantile_batched(void* stream, int32_t n_views, const q
                                           size_t workspace_bytes) {
   if (n_views <= 0 || n_views > (1 << (32 - kViewShift)))
     return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: n_views = %d out of range", n_views);
-  if (!views || !schedule || !workspace || !prm)
+  if (!views || !schedule || !prm)
     return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: null pointer");
-  if (workspace_bytes < sizeof(uint32_t))
-    return fail(QR_ERR_CAPACITY, "qr_render_quantile_batched: workspace needs 4 bytes");
-  if (n_items < 0 || n_items >= (1ll << 32))
+  if (n_workgroups < 0) return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: n_workgroups < 0");
+  if (n_workgroups > 0 && (!workspace || workspace_bytes < sizeof(uint32_t)))
+    return fail(QR_ERR_CAPACITY, "qr_render_quantile_batched: persistent mode needs a 4-byte workspace");
+  if (n_items < 0 || n_items >= (1ll << 31))
     return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: bad item count");
-  if (n_workgroups <= 0) return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: n_workgroups <= 0");
   if (K < 1 || K > QR_MAX_K)
     return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile_batched: K = %d outside [1, %d]", K, QR_MAX_K);
   if (dtype != QR_F32 && dtype != QR_BF16 && dtype != QR_FP8_E4M3)
@@ -374,9 +458,22 @@ extern "C" int qr_render_quantile_batched(void* stream, int32_t n_views, const q
     return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: need 0 < alpha_min <= alpha_max < 1");
   if (n_items == 0) return QR_OK;
   hipStream_t s = as_stream(stream);
+  const size_t lds = static_cast<size_t>(kTilePix) * ((K + 3) & ~3) * (sizeof(int) + sizeof(float));
+  if (n_workgroups == 0) {
+    const int ni = static_cast<int>(n_items);
+#define QR_LAUNCH(DT)                                                                            \
+  hipLaunchKernelGGL(render_quantile_batched_grid_kernel<DT>, dim3(ni), dim3(kTilePix), lds, s, \
+                     views, schedule, ni, *prm, K, dim)
+    switch (dtype) {
+      case QR_F32: QR_LAUNCH(QR_F32); break;
+      case QR_BF16: QR_LAUNCH(QR_BF16); break;
+      default: QR_LAUNCH(QR_FP8_E4M3); break;
+    }
+#undef QR_LAUNCH
+    return check_launch("qr_render_quantile_batched");
+  }
   auto* counter = static_cast<uint32_t*>(workspace);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
-  const size_t lds = static_cast<size_t>(kTilePix) * ((K + 3) & ~3) * (sizeof(int) + sizeof(float));
 #define QR_LAUNCH(DT)                                                                             \
   hipLaunchKernelGGL(render_quantile_batched_kernel<DT>, dim3(n_workgroups), dim3(kTilePix), lds, \
                      s, views, schedule, n_items, counter, *prm, K, dim)

@@ -29,14 +29,23 @@ schedule_zero_kernel(uint32_t* __restrict__ a) {
   if (threadIdx.x < 2 * kBuckets) a[threadIdx.x] = 0u;
 }
 
+// Per-workgroup histogram in LDS, then one global atomic per non-empty
+// bucket: a batch has few length classes, so per-item global atomics would
+// all land on a handful of words.
 __global__ void __launch_bounds__(256)
 schedule_count_kernel(int64_t n_items, int n_views, const int32_t* __restrict__ view_first,
                       const qr_view* __restrict__ views, uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t h[kBuckets];
+  if (threadIdx.x < kBuckets) h[threadIdx.x] = 0u;
+  __syncthreads();
   const int64_t i = blockIdx.x * 256LL + threadIdx.x;
-  if (i >= n_items) return;
-  int v, t;
-  item_of(i, n_views, view_first, &v, &t);
-  atomicAdd(&cnt[heavy_rank(views, v, t)], 1u);
+  if (i < n_items) {
+    int v, t;
+    item_of(i, n_views, view_first, &v, &t);
+    atomicAdd(&h[heavy_rank(views, v, t)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kBuckets && h[threadIdx.x] != 0u) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
 }
 
 __global__ void schedule_scan_kernel(uint32_t* __restrict__ cnt) {
@@ -50,17 +59,31 @@ __global__ void schedule_scan_kernel(uint32_t* __restrict__ cnt) {
   }
 }
 
+// Items of a workgroup take consecutive slots of their bucket: local ranks
+// from LDS atomics, one global reservation per bucket and workgroup. The
+// order inside a bucket is unspecified.
 __global__ void __launch_bounds__(256)
 schedule_scatter_kernel(int64_t n_items, int n_views, const int32_t* __restrict__ view_first,
                         const qr_view* __restrict__ views, const uint32_t* __restrict__ start,
                         uint32_t* __restrict__ cursor, uint32_t* __restrict__ schedule) {
+  __shared__ uint32_t h[kBuckets];
+  __shared__ uint32_t base[kBuckets];
+  if (threadIdx.x < kBuckets) h[threadIdx.x] = 0u;
+  __syncthreads();
   const int64_t i = blockIdx.x * 256LL + threadIdx.x;
-  if (i >= n_items) return;
-  int v, t;
-  item_of(i, n_views, view_first, &v, &t);
-  const int b = heavy_rank(views, v, t);
-  const uint32_t pos = start[b] + atomicAdd(&cursor[b], 1u);
-  schedule[pos] = (static_cast<uint32_t>(v) << QR_BATCH_TILE_BITS) | static_cast<uint32_t>(t);
+  int v = 0, t = 0, b = 0;
+  uint32_t local = 0u;
+  if (i < n_items) {
+    item_of(i, n_views, view_first, &v, &t);
+    b = heavy_rank(views, v, t);
+    local = atomicAdd(&h[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kBuckets && h[threadIdx.x] != 0u)
+    base[threadIdx.x] = start[threadIdx.x] + atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]);
+  __syncthreads();
+  if (i < n_items)
+    schedule[base[b] + local] = (static_cast<uint32_t>(v) << QR_BATCH_TILE_BITS) | static_cast<uint32_t>(t);
 }
 
 }  // namespace qr

@@ -7,6 +7,7 @@ pipeline runs in the HIP kernels of libqrender.so.
 
 from __future__ import annotations
 
+import ctypes
 import dataclasses
 
 import torch
@@ -66,6 +67,18 @@ def project(means3d, scales, quats, opacity, camera, params: RenderParams = Rend
     return pr
 
 
+def project_views(means3d, scales, quats, opacity, cameras, params: RenderParams = RenderParams(),
+                  out: Projected | None = None, stream=None) -> Projected:
+    """Projection of the scene into every camera of a batch (one image size)
+    in one launch per 32 cameras; record v*N + i is Gaussian i in view v."""
+    n = means3d.shape[0]
+    cams = cameras if isinstance(cameras, ctypes.Array) else L.make_cameras(cameras)
+    pr = out if out is not None else alloc_projected(len(cams) * n, means3d.device)
+    L.qr_project_views(means3d, scales, quats, opacity, cams, params.c(), pr.means2d,
+                       pr.conic_opacity, pr.depth, pr.tile_rect, pr.tiles_touched, stream=stream)
+    return pr
+
+
 def count_pairs(pr: Projected, stream=None) -> int:
     ws = torch.empty(1, dtype=torch.int64, device=pr.depth.device)
     return L.qr_count_pairs(pr.tiles_touched, ws, stream=stream)
@@ -94,6 +107,48 @@ class Binner:
                       self.capacity, self.workspace, b.sorted_gid, b.sorted_keys, b.tile_offsets,
                       b.total_pairs, stream=stream)
         return b
+
+
+class ViewsBinner:
+    """bin_sort_views workspace and outputs for a batch of n_views views of
+    n_per_view Gaussians each: view v's tile lists are tiles
+    [v*T, (v+1)*T) of one stacked grid (T tiles per view) and hold
+    view-local Gaussian ids."""
+
+    def __init__(self, n_views: int, n_per_view: int, width: int, height: int, capacity: int,
+                 device="cuda", keep_keys: bool = False):
+        self.n_views, self.n_per_view = n_views, n_per_view
+        self.width, self.height = width, height
+        self.tiles_x, self.tiles_y = tiles_of(width, height)
+        self.tiles_per_view = self.tiles_x * self.tiles_y
+        self.capacity = int(capacity)
+        nb = L.qr_bin_sort_workspace_size(n_views * n_per_view, self.tiles_x, n_views * self.tiles_y,
+                                          self.capacity)
+        self.workspace = torch.empty(nb, dtype=torch.uint8, device=device)
+        i32 = dict(dtype=torch.int32, device=device)
+        self.bins = Bins(torch.empty(n_views * self.tiles_per_view + 1, **i32),
+                         torch.empty(max(self.capacity, 1), **i32), torch.empty(1, **i32),
+                         self.capacity,
+                         torch.empty(max(self.capacity, 1), dtype=torch.int64, device=device)
+                         if keep_keys else None)
+
+    def __call__(self, pr: Projected, stream=None) -> Bins:
+        b = self.bins
+        L.qr_bin_sort_views(self.n_views, self.n_per_view, self.tiles_x, self.tiles_y, pr.tile_rect,
+                            pr.tiles_touched, pr.depth, self.capacity, self.workspace, b.sorted_gid,
+                            b.sorted_keys, b.tile_offsets, b.total_pairs, stream=stream)
+        return b
+
+    def view(self, pr: Projected, v: int):
+        """(Projected, Bins) of view v as views into the batch buffers (no
+        copies), usable wherever a single view's projection and bins are."""
+        n, T = self.n_per_view, self.tiles_per_view
+        s = slice(v * n, (v + 1) * n)
+        b = self.bins
+        return (Projected(pr.means2d[s], pr.conic_opacity[s], pr.depth[s], pr.tile_rect[s],
+                          pr.tiles_touched[s]),
+                Bins(b.tile_offsets[v * T:(v + 1) * T + 1], b.sorted_gid, b.total_pairs,
+                     b.capacity, b.sorted_keys))
 
 
 def bin_sort(pr: Projected, width: int, height: int, capacity: int | None = None,

@@ -111,6 +111,60 @@ def test_render_validation(L):
     assert rc == L.QR_ERR_INVALID_ARG
 
 
+def test_batched_validation(L):
+    lib = L.lib()
+    prm = L.make_params()
+    P = ctypes.byref(prm)
+    d = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+    def b(n_views, n_items, n_wg, ws, ws_bytes, K=8, dtype=0, dim=16):
+        return lib.qr_render_quantile_batched(None, n_views, d, P, K, dtype, dim, d, n_items,
+                                              n_wg, ws, ws_bytes)
+
+    assert b(0, 10, 0, None, 0) == L.QR_ERR_INVALID_ARG
+    assert b(1, 10, -1, None, 0) == L.QR_ERR_INVALID_ARG
+    assert b(1, 10, 4, None, 0) == L.QR_ERR_CAPACITY  # persistent mode needs the counter
+    assert b(1, 10, 4, d, 2) == L.QR_ERR_CAPACITY
+    assert b(1, 1 << 31, 0, None, 0) == L.QR_ERR_INVALID_ARG
+    assert b(1, 10, 0, None, 0, K=0) == L.QR_ERR_UNSUPPORTED
+    assert b(1, 10, 0, None, 0, dtype=9) == L.QR_ERR_UNSUPPORTED
+    assert b(1, 10, 0, None, 0, dim=24) == L.QR_ERR_UNSUPPORTED
+    assert b(1, 0, 0, None, 0) == L.QR_OK  # nothing to render: no launch
+    rc = lib.qr_batch_schedule(None, 0, d, d, 10, d, d, 256)
+    assert rc == L.QR_ERR_INVALID_ARG
+    rc = lib.qr_batch_schedule(None, 2, d, d, 10, d, d, 16)
+    assert rc == L.QR_ERR_CAPACITY
+
+
+def test_views_front_validation(L):
+    lib = L.lib()
+    prm = L.make_params()
+    d = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    mk = lambda **kw: dict(dict(R_cw=[1, 0, 0, 0, 1, 0, 0, 0, 1], t=[0, 0, 3], fx=50.0, fy=50.0,
+                                cx=32.0, cy=32.0, width=64, height=64, z_near=0.2), **kw)
+    cams = L.make_cameras([type("C", (), mk())(), type("C", (), mk(t=[0, 0, 4]))()])
+    pv = lambda n, nv, cs: lib.qr_project_views(None, n, d, d, d, d, nv, cs, ctypes.byref(prm),
+                                                d, d, d, d, d)
+    assert pv(10, 0, cams) == L.QR_ERR_INVALID_ARG
+    assert pv(-1, 2, cams) == L.QR_ERR_INVALID_ARG
+    other = L.make_cameras([type("C", (), mk())(), type("C", (), mk(width=80))()])
+    rc = pv(10, 2, other)
+    assert rc == L.QR_ERR_INVALID_ARG and "image size" in L.last_error()
+    bad = L.make_cameras([type("C", (), mk())(), type("C", (), mk(fx=0.0))()])
+    assert pv(10, 2, bad) == L.QR_ERR_INVALID_ARG
+    assert pv(0, 2, cams) == L.QR_OK  # no Gaussians: nothing to launch
+    rc = lib.qr_project_views(None, 10, None, d, d, d, 2, cams, ctypes.byref(prm), d, d, d, d, d)
+    assert rc == L.QR_ERR_INVALID_ARG
+    bs = lambda nv, npv, ws_bytes: lib.qr_bin_sort_views(None, nv, npv, 4, 4, d, d, d, 5000, d,
+                                                         ws_bytes, d, None, d, d)
+    assert bs(0, 100, 1 << 30) == L.QR_ERR_INVALID_ARG
+    assert bs(2, -1, 1 << 30) == L.QR_ERR_INVALID_ARG
+    out = ctypes.c_size_t(0)
+    assert lib.qr_bin_sort_workspace_size(3 * 100, 4, 3 * 4, 5000, ctypes.byref(out)) == L.QR_OK
+    assert bs(3, 100, out.value - 1) == L.QR_ERR_CAPACITY
+    assert bs(2, 1 << 32, 1 << 30) == L.QR_ERR_UNSUPPORTED
+
+
 def test_count_pairs_validation(L):
     lib = L.lib()
     out = ctypes.c_uint64(7)

@@ -61,7 +61,7 @@ def test_batched_matches_single_view_kernel(qr, storage):
     code = L.QR_F32 if storage == "f32" else L.QR_FP8_E4M3
     bq = BatchedQuantile(views, K, 32, code, qr.RenderParams().c())
     for kind in ("natural", "heavy"):
-        for w in (1, 3, 8):
+        for w in (0, 1, 3, 8):
             for v in views:
                 v["out"].fill_(float("nan"))
                 v["n_sel"].fill_(-7)
@@ -97,8 +97,8 @@ def test_autotuner_picks_a_candidate_and_caches(qr, tmp_path):
     views, _ = _make_views(qr)
     bq = BatchedQuantile(views, 8, 32, L.QR_F32, qr.RenderParams().c())
     path = str(tmp_path / "tune.json")
-    cfg, timings = autotune(bq, wg_per_cu=(1, 4), reps=2, cache_path=path)
-    assert cfg["schedule"] in ("natural", "heavy") and cfg["wg_per_cu"] in (1, 4)
+    cfg, timings = autotune(bq, wg_per_cu=(0, 4), reps=2, cache_path=path)
+    assert cfg["schedule"] in ("natural", "heavy") and cfg["wg_per_cu"] in (0, 4)
     assert len(timings) == 4
     cfg2, timings2 = autotune(bq, cache_path=path)
     assert cfg2 == cfg and timings2 == {}

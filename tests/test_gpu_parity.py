@@ -130,16 +130,20 @@ def test_projection_matches_oracle(qr):
         assert np.mean(np.any(rect_diff > 0, axis=1)) < 1e-3
 
 
-@pytest.mark.parametrize("case", ["tiny", "ragged", "room"])
+@pytest.mark.parametrize("case", ["tiny", "ragged", "room", "many_tiles"])
 def test_bin_sort_bit_exact(qr, case):
+    """"many_tiles" (3840 x 2400: 36,000 tiles) takes the multi-workgroup
+    scan of the tile counters; the other images the single-workgroup one."""
     if case == "tiny":
         sc, cam = synth.make_tiny(0), synth.tiny_camera()
     elif case == "ragged":
         sc, cam = synth.make_tiny(3, n=3000, dim=16), synth.tiny_camera(100)
         cam.height = 75
         cam.cy = 37.5
-    else:
+    elif case == "room":
         sc, cam = synth.make_room(200_000, 1, dim=16), synth.room_camera(100)
+    else:
+        sc, cam = synth.make_room(20_000, 4, dim=16), synth.room_camera(101, 3840, 2400, 3462.0)
     res = gpu_pipeline(qr, sc, cam, 8, dense=False, debug=False)
     tx, ty = (cam.width + 15) // 16, (cam.height + 15) // 16
     g = res["pr"]
