@@ -299,8 +299,16 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
       ++cnt;
     }
     L.unum[grp] = cnt;
-    // positions -> Gaussian ids (independent loads)
-    for (int e = 0; e < cnt; ++e) L.ugid[grp * kUCap + e] = static_cast<int>(v.sorted_gid[L.ugid[grp * kUCap + e]]);
+    // positions -> Gaussian ids: all loads issued before any result is used
+    int pos[kUCap];
+#pragma unroll
+    for (int e = 0; e < kUCap; ++e) pos[e] = e < cnt ? L.ugid[grp * kUCap + e] : -1;
+    uint32_t gid[kUCap];
+#pragma unroll
+    for (int e = 0; e < kUCap; ++e) gid[e] = pos[e] >= 0 ? v.sorted_gid[pos[e]] : 0u;
+#pragma unroll
+    for (int e = 0; e < kUCap; ++e)
+      if (e < cnt) L.ugid[grp * kUCap + e] = static_cast<int>(gid[e]);
   }
   wave_lds_sync();
   for (int gl = 0; gl < kWaveGroups; ++gl) {
