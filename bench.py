@@ -127,24 +127,32 @@ class BatchState:
     one stacked tile grid (one launch sequence), and the device view table of
     the batched Q-Render launch over all (pose, tile) items."""
 
-    def __init__(self, qr, L, scene_t, cams, W, H, capacity, outs, aux_f, aux_i, K, dim):
+    def __init__(self, qr, L, scene_t, cams, W, H, capacity, outs, aux_f, aux_i, K, dim,
+                 dtype_code=None, scale=None):
         import torch
-        from paper_2512_20927_amd.batched import BatchedQuantile
         n = scene_t["means"].shape[0]
-        self.L, self.s, self.W, self.H = L, scene_t, W, H
+        self.L, self.s, self.W, self.H, self.dim = L, scene_t, W, H, dim
+        self.dtype_code = L.QR_F32 if dtype_code is None else dtype_code
+        self.scale = scale
         self.cams_c = L.make_cameras(cams)
         self.prm = qr.RenderParams().c()
         self.pv = qr.render.alloc_projected(len(cams) * n)
         self.vb = qr.ViewsBinner(len(cams), n, W, H, capacity)
         self.outs, self.aux_f, self.aux_i = outs, aux_f, aux_i
         self.per_view = [self.vb.view(self.pv, v) for v in range(len(cams))]
-        views = [dict(tile_offsets=b.tile_offsets, sorted_gid=b.sorted_gid, means2d=pr.means2d,
-                      conic_opacity=pr.conic_opacity, features=scene_t["feats"], feature_scale=None,
-                      out=outs[v], T_q=aux_f[v], n_sel=aux_i[v], width=W, height=H)
-                 for v, (pr, b) in enumerate(self.per_view)]
-        self.bq = BatchedQuantile(views, K, dim, L.QR_F32, self.prm)
+        self.bq = self.make_bq(K)
         self.front_done = torch.cuda.Event()
         self.render_done = torch.cuda.Event()
+
+    def make_bq(self, K):
+        """A batched Q-Render launch over all views of this state for K."""
+        from paper_2512_20927_amd.batched import BatchedQuantile
+        views = [dict(tile_offsets=b.tile_offsets, sorted_gid=b.sorted_gid, means2d=pr.means2d,
+                      conic_opacity=pr.conic_opacity, features=self.s["feats"],
+                      feature_scale=self.scale, out=self.outs[v], T_q=self.aux_f[v],
+                      n_sel=self.aux_i[v], width=self.W, height=self.H)
+                 for v, (pr, b) in enumerate(self.per_view)]
+        return BatchedQuantile(views, K, self.dim, self.dtype_code, self.prm)
 
     def front(self):
         s, pv = self.s, self.pv
@@ -156,7 +164,7 @@ class BatchState:
     def render_dense(self):
         for v, (pr, b) in enumerate(self.per_view):
             self.L.qr_render_dense(self.W, self.H, self.prm, b.tile_offsets, b.sorted_gid, pr.means2d,
-                                   pr.conic_opacity, self.s["feats"], None, self.outs[v],
+                                   pr.conic_opacity, self.s["feats"], self.scale, self.outs[v],
                                    self.aux_f[v], self.aux_i[v])
 
 
@@ -419,40 +427,55 @@ def run_room(args):
 
 
 def run_precision(args):
-    """1M Gaussians, 1296x968, 512-D bf16 features: Q-Render K in {4, 8, 16}
-    and the dense blend, 4 views."""
+    """1M Gaussians, 1296x968, 512-D bf16 features: 4 poses per step through
+    the batched path (one projection launch, one stacked binning, one batched
+    Q-Render launch) for K in {4, 8, 16}, and the dense blend."""
     import torch
     import paper_2512_20927_amd as qr
     from paper_2512_20927_amd import _lib as L
+    from paper_2512_20927_amd.batched import autotune
     import synth
     cfg = synth.CONFIGS["precision"]
     sc = synth.make_room(cfg["n"], cfg["seed"], dim=cfg["dim"])
     cams = synth.room_poses(cfg["pose_seeds"], cfg["width"], cfg["height"], cfg["fx"])
+    W, H, D = cfg["width"], cfg["height"], cfg["dim"]
     s = _scene_tensors(sc, torch)
     f32 = torch.from_numpy(sc.features).cuda()
-    feats, _ = qr.quantize(f32, "bf16")
-    del f32
-    s["feats"] = feats
-    pairs = []
-    for c in cams:
-        pr = qr.project(s["means"], s["scales"], s["quats"], s["opacity"], c)
-        pairs.append(qr.count_pairs(pr))
-    cap = int(max(pairs) * 1.05) + 1024
-    per_k, render_ms = {}, {}
+    s["feats"], _ = qr.quantize(f32, "bf16")
+    del f32, sc
+    pv = qr.project_views(s["means"], s["scales"], s["quats"], s["opacity"], cams)
+    capacity = int(qr.count_pairs(pv) * 1.05) + 1024
+    del pv
+    nv = len(cams)
+    outs = [torch.empty(H, W, D, device="cuda") for _ in range(nv)]
+    aux_f = [torch.empty(H, W, device="cuda") for _ in range(nv)]
+    aux_i = [torch.empty(H, W, dtype=torch.int32, device="cuda") for _ in range(nv)]
+    states = [BatchState(qr, L, s, cams, W, H, capacity, outs, aux_f, aux_i, 8, D,
+                         dtype_code=L.QR_BF16) for _ in range(2)]
+    for st in states:
+        st.front()
+    torch.cuda.synchronize()
+    pairs = [int(b.tile_offsets[-1].item() - b.tile_offsets[0].item()) for _, b in states[0].per_view]
+    per_k, render_ms, tuned_k = {}, {}, {}
+    frames = args.steps * nv
     for K in cfg["Ks"]:
-        runner = FrameRunner(qr, L, s, cams, K, cap, cfg["dim"], feats=feats)
-        dt, kms = timed(runner, "q", args.steps, args.warmup, len(cams))
-        per_k[str(K)] = round(args.steps * len(cams) / dt, 2)
+        for st in states:
+            st.bq = st.make_bq(K)
+        tuned, _ = autotune(states[0].bq, wg_per_cu=(0, 3, 8), use_cache=False)
+        dt, kms = timed_batched(states, args.steps, args.warmup, tuned["schedule"], tuned["wg_per_cu"])
+        per_k[str(K)] = round(frames / dt, 2)
         render_ms[str(K)] = round(kms, 4)
-    dt_d, kms_d = timed(runner, "d", args.steps, args.warmup, len(cams))
-    d_fps = args.steps * len(cams) / dt_d
+        tuned_k[str(K)] = {k: tuned[k] for k in ("schedule", "wg_per_cu")}
+    dt_d = timed_dense(states[0], args.steps, args.warmup)
+    d_fps = frames / dt_d
     rec = _base_record(args, per_k["8"], "frames/s", "bf16",
                        "precision: 1M Gaussians, 1296x968, fx=fy=1168.4, 512-D bf16 features "
                        "(float32 accumulation), 4 poses per step; value = Q-Render K=8",
-                       1e3 * args.steps * len(cams) / per_k["8"] / args.steps)
+                       1e3 * frames / per_k["8"] / args.steps)
     rec.update({"q_fps_per_K": per_k, "dense_value": round(d_fps, 2),
                 "q_over_dense": round(per_k["8"] / d_fps, 3),
-                "render_ms": {"quantile_per_K": render_ms, "dense": round(kms_d, 4)},
+                "render_ms": {"quantile_batched_launch_per_K": render_ms},
+                "batched_launch_per_K": tuned_k,
                 "workload_stats": {"pairs_mean": float(np.mean(pairs))}})
     print(json.dumps(rec))
 
@@ -515,11 +538,11 @@ def run_diff(args):
 
 def run_batched(args):
     """32 views over 4 scenes (0.3M, 0.8M, 1.5M, 3M Gaussians) at 1280x720,
-    512-D fp8 e4m3 features with per-Gaussian scales: per batch, every view
-    is projected and binned, a device-built schedule orders the (view, tile)
-    items and one persistent launch renders all of them (K=8); the
-    autotuner's choice of schedule and workgroups is used. Then the
-    Q-Render backward of every view."""
+    512-D fp8 e4m3 features with per-Gaussian scales: per batch, each scene is
+    projected into its 8 views in one launch and binned over their stacked
+    tile grid, a device-built schedule orders the (view, tile) items and one
+    launch renders all of them (K=8); the autotuner's choice of schedule and
+    launch shape is used. Then the Q-Render backward of every view."""
     import torch
     import paper_2512_20927_amd as qr
     from paper_2512_20927_amd import _lib as L
@@ -527,7 +550,9 @@ def run_batched(args):
     import synth
     K, D, W, H = 8, 512, 1280, 720
     sizes, seeds, per = (300_000, 800_000, 1_500_000, 3_000_000), (10, 11, 12, 13), 8
-    scenes = []
+    prm_c = qr.RenderParams().c()
+    scenes, fronts = [], []
+    seed = 300
     for n, sd in zip(sizes, seeds):
         sc = synth.make_room(n, sd, dim=D)
         st = _scene_tensors(sc, torch)
@@ -535,51 +560,32 @@ def run_batched(args):
         st["codes"], st["scale"] = qr.quantize(f32, "fp8")
         del f32, sc
         scenes.append(st)
-    prm = qr.RenderParams()
-    cams, scene_of = [], []
-    seed = 300
-    for si in range(len(sizes)):
-        for _ in range(per):
-            cams.append(synth.room_camera(seed, W, H, 1154.0))
-            scene_of.append(si)
-            seed += 1
-    n_views = len(cams)
-    prs, binners, views = [], [], []
-    ws = None
-    for c, si in zip(cams, scene_of):
-        st = scenes[si]
-        pr = qr.project(st["means"], st["scales"], st["quats"], st["opacity"], c)
-        cap = int(qr.count_pairs(pr) * 1.05) + 1024
-        b = qr.Binner(st["means"].shape[0], W, H, cap)
-        if ws is None or ws.numel() < b.workspace.numel():
-            ws = b.workspace
-        b.workspace = None
-        prs.append(pr)
-        binners.append(b)
-    for b in binners:  # one shared binning workspace (views are binned in turn)
-        b.workspace = ws
-    outs = [torch.empty(H, W, D, device="cuda") for _ in range(n_views)]
-    for v in range(n_views):
-        st = scenes[scene_of[v]]
-        bins = binners[v].bins
-        views.append(dict(tile_offsets=bins.tile_offsets, sorted_gid=bins.sorted_gid,
-                          means2d=prs[v].means2d, conic_opacity=prs[v].conic_opacity,
-                          features=st["codes"], feature_scale=st["scale"], out=outs[v],
-                          T_q=None, n_sel=None, width=W, height=H))
-    cam_c = [L.make_camera(c) for c in cams]
-    prm_c = prm.c()
+        cams = [synth.room_camera(seed + k, W, H, 1154.0) for k in range(per)]
+        seed += per
+        pv = qr.project_views(st["means"], st["scales"], st["quats"], st["opacity"], cams)
+        vb = qr.ViewsBinner(per, n, W, H, int(qr.count_pairs(pv) * 1.05) + 1024)
+        fronts.append((L.make_cameras(cams), pv, vb))
+    n_views = per * len(sizes)
 
     def front():
-        for v in range(n_views):
-            st = scenes[scene_of[v]]
-            pr = prs[v]
-            L.qr_project(st["means"], st["scales"], st["quats"], st["opacity"], cam_c[v], prm_c,
-                         pr.means2d, pr.conic_opacity, pr.depth, pr.tile_rect, pr.tiles_touched)
-            binners[v](pr)
+        for st, (cams_c, pv, vb) in zip(scenes, fronts):
+            L.qr_project_views(st["means"], st["scales"], st["quats"], st["opacity"], cams_c, prm_c,
+                               pv.means2d, pv.conic_opacity, pv.depth, pv.tile_rect, pv.tiles_touched)
+            vb(pv)
 
     front()
+    outs = [torch.empty(H, W, D, device="cuda") for _ in range(n_views)]
+    views, per_view = [], []
+    for si, (st, (_, pv, vb)) in enumerate(zip(scenes, fronts)):
+        for k in range(per):
+            prv, bv = vb.view(pv, k)
+            per_view.append((si, prv, bv))
+            views.append(dict(tile_offsets=bv.tile_offsets, sorted_gid=bv.sorted_gid,
+                              means2d=prv.means2d, conic_opacity=prv.conic_opacity,
+                              features=st["codes"], feature_scale=st["scale"],
+                              out=outs[len(views)], T_q=None, n_sel=None, width=W, height=H))
     bq = BatchedQuantile(views, K, D, L.QR_FP8_E4M3, prm_c)
-    tuned, timings = autotune(bq, use_cache=False)
+    tuned, timings = autotune(bq, wg_per_cu=(0, 3, 8), use_cache=False)
     for _ in range(args.warmup):
         front()
         bq.render(tuned["schedule"], tuned["wg_per_cu"])
@@ -594,28 +600,27 @@ def run_batched(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     render_ms = float(np.mean([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(args.steps)]))
-    # backward of every view (non-batched kernel), one grad_out buffer reused
+    # backward of every view (per-view kernel), one grad_out buffer reused
     gout = torch.randn(H, W, D, device="cuda")
     gfs = [torch.zeros(st["means"].shape[0], D, device="cuda") for st in scenes]
     gms = [torch.zeros(st["means"].shape[0], 2, device="cuda") for st in scenes]
     gcs = [torch.zeros(st["means"].shape[0], 4, device="cuda") for st in scenes]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for v in range(n_views):
-        si = scene_of[v]
+    for si, prv, bv in per_view:
         st = scenes[si]
-        b = binners[v].bins
-        L.qr_render_quantile_backward(W, H, prm_c, K, b.tile_offsets, b.sorted_gid, prs[v].means2d,
-                                      prs[v].conic_opacity, st["codes"], st["scale"], gout,
+        L.qr_render_quantile_backward(W, H, prm_c, K, bv.tile_offsets, bv.sorted_gid, prv.means2d,
+                                      prv.conic_opacity, st["codes"], st["scale"], gout,
                                       gfs[si], gms[si], gcs[si])
     torch.cuda.synchronize()
     bwd_s = time.perf_counter() - t1
     rec = _base_record(args, n_views * args.steps / dt, "views/s", "fp8",
                        "batched: 32 views over 4 room scenes (0.3M/0.8M/1.5M/3M Gaussians), "
                        "1280x720, fx=fy=1154, 512-D fp8 e4m3 features with per-Gaussian scale, "
-                       "Q-Render K=8, one persistent launch per batch",
+                       "Q-Render K=8, one launch per batch",
                        dt / args.steps * 1e3)
-    rec.update({"render_ms_per_batch": round(render_ms, 3), "autotuned": tuned,
+    rec.update({"render_ms_per_batch": round(render_ms, 3),
+                "autotuned": {k: tuned[k] for k in ("schedule", "wg_per_cu")},
                 "autotune_ms": {k: round(v, 3) for k, v in timings.items()},
                 "backward_views_per_s": round(n_views / bwd_s, 2)})
     print(json.dumps(rec))

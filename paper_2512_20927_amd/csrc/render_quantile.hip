@@ -214,6 +214,7 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
   float T = 1.f, TQ = 1.f;
   int k = 0, ns = 0;
   bool done = !inside;
+  float thr_k = quantile_threshold(1, K);  // t_{k+1}: changes only at a crossing
   const int KP = (K + 3) & ~3;  // selection row stride: 16-byte aligned rows
   int* s_sel_pos = s_sel_gid;  // selections are kept as tile-list positions
   int* my_pos = s_sel_pos + tid * KP;
@@ -232,21 +233,32 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
       L.co[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     __syncthreads();
-    const int cnt4 = (min(kTilePix, hi - batch) + 3) & ~3;
-    for (int j = 0; j < cnt4; j += 4) {
+    // kWalkUnroll records are read from LDS before any is used (one LDS round
+    // trip per group of records; the padding makes every group whole)
+    constexpr int kWalkUnroll = 8;
+    const int cnt_pad = (min(kTilePix, hi - batch) + kWalkUnroll - 1) & ~(kWalkUnroll - 1);
+    for (int j = 0; j < cnt_pad; j += kWalkUnroll) {
       if (__all(done)) break;
+      float2 rm[kWalkUnroll];
+      float4 rc[kWalkUnroll];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const float alpha = gauss_alpha(L.mean[j + u], L.co[j + u], pxc, pyc, amax);
+      for (int u = 0; u < kWalkUnroll; ++u) {
+        rm[u] = L.mean[j + u];
+        rc[u] = L.co[j + u];
+      }
+#pragma unroll
+      for (int u = 0; u < kWalkUnroll; ++u) {
+        const float alpha = gauss_alpha(rm[u], rc[u], pxc, pyc, amax);
         if (done || alpha < amin) continue;  // finished, or not on this pixel's ray
         const float T_test = T * (1.f - alpha);
-        if (T_test < L.thr[k]) {  // crossing: a quantile Gaussian
+        if (T_test < thr_k) {  // crossing: a quantile Gaussian
           my_pos[ns] = batch + j + u;
           my_w[ns] = TQ * alpha;
           ++ns;
           TQ = TQ * (1.f - alpha);
           ++k;
           while (k < K && T_test < L.thr[k]) ++k;  // thresholds crossed by the same step
+          thr_k = L.thr[k];
           if (k == K) done = true;
         }
         T = T_test;
@@ -268,18 +280,19 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
   if (lane < kWaveGroups) {
     const int grp = wave * kWaveGroups + lane;
     const int p0 = grp * kPG;
-    int n[kPG], idx[kPG];
+    // each pixel's next selection (list position and weight) kept in registers
+    int n[kPG], idx[kPG], head[kPG];
+    float hw[kPG];
 #pragma unroll
     for (int q = 0; q < kPG; ++q) {
       n[q] = max(L.ns[p0 + q], 0);
       idx[q] = 0;
+      head[q] = n[q] > 0 ? s_sel_pos[(p0 + q) * KP] : 0x7fffffff;
+      hw[q] = n[q] > 0 ? s_sel_w[(p0 + q) * KP] : 0.f;
     }
     int cnt = 0;
     for (;;) {
-      int best = 0x7fffffff;
-#pragma unroll
-      for (int q = 0; q < kPG; ++q)
-        if (idx[q] < n[q]) best = min(best, s_sel_pos[(p0 + q) * KP + idx[q]]);
+      const int best = min(min(head[0], head[1]), min(head[2], head[3]));
       if (best == 0x7fffffff) break;
       if (cnt == kUCap) {
         cnt = -1;
@@ -289,9 +302,11 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
 #pragma unroll
       for (int q = 0; q < kPG; ++q) {
         wq[q] = 0.f;
-        if (idx[q] < n[q] && s_sel_pos[(p0 + q) * KP + idx[q]] == best) {
-          wq[q] = s_sel_w[(p0 + q) * KP + idx[q]];
+        if (head[q] == best) {
+          wq[q] = hw[q];
           ++idx[q];
+          head[q] = idx[q] < n[q] ? s_sel_pos[(p0 + q) * KP + idx[q]] : 0x7fffffff;
+          hw[q] = idx[q] < n[q] ? s_sel_w[(p0 + q) * KP + idx[q]] : 0.f;
         }
       }
       L.ugid[grp * kUCap + cnt] = best;  // position for now
