@@ -11,9 +11,10 @@
 //      cursor and stores the 64-bit key (float bits of depth << 32 | id);
 //   4. sort: one workgroup per tile sorts its bucket. The keys are unique
 //      (they contain the id), so the result is the exact (depth, id) order
-//      whatever order step 3 produced. Buckets of up to kLdsItems keys are
-//      bitonic-sorted in LDS; longer ones take a single-workgroup LSD radix
-//      sort through global scratch.
+//      whatever order step 3 produced. Buckets of up to 256 keys are
+//      bitonic-sorted one key per thread (lane shuffles inside a wave, LDS
+//      across waves), up to kLdsItems in LDS; longer ones take a
+//      single-workgroup LSD radix sort through global scratch.
 // Depth is positive (z > z_near > 0), so its IEEE bit pattern orders like
 // the value. No kernel synchronises with the host: grids are sized by the
 // caller's capacity and every kernel reads the pair count from device memory.
@@ -232,6 +233,12 @@ __device__ __forceinline__ void stable_scatter_round(bool valid, unsigned long l
   __syncthreads();
 }
 
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int mask) {
+  const uint32_t lo = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v & 0xFFFFFFFFull), mask, 64));
+  const uint32_t hi = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v >> 32), mask, 64));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
 __global__ void __launch_bounds__(256)
 tile_sort_kernel(int n_tiles, const uint32_t* __restrict__ offsets, int64_t capacity,
                  int gid_bits, unsigned long long* __restrict__ bucket,
@@ -247,6 +254,38 @@ tile_sort_kernel(int n_tiles, const uint32_t* __restrict__ offsets, int64_t capa
   const int n = static_cast<int>(hi - lo);
   if (n <= 0) return;
   const unsigned long long tile_hi = static_cast<unsigned long long>(t) << 32;
+
+  if (n <= 256) {
+    // bitonic sort with one key per thread (padded with the largest key):
+    // partners in the same wave (distance < 64) are read with lane
+    // shuffles, so only the few steps across waves go through LDS and a
+    // workgroup barrier
+    const int i = threadIdx.x;
+    int size = 1;
+    while (size < n) size <<= 1;
+    unsigned long long key = i < n ? bucket[lo + i] : ~0ull;
+    for (int k = 2; k <= size; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        unsigned long long other;
+        if (j < 64) {
+          other = shfl_xor_u64(key, j);
+        } else {
+          s_key[i] = key;
+          __syncthreads();
+          other = s_key[i ^ j];
+          __syncthreads();
+        }
+        const bool ascending = (i & k) == 0;
+        const bool lower = (i & j) == 0;  // i is the smaller index of the pair
+        key = (lower == ascending) ? (key < other ? key : other) : (key < other ? other : key);
+      }
+    }
+    if (i < n) {
+      sorted_gid[lo + i] = static_cast<uint32_t>(key);
+      if (sorted_keys) sorted_keys[lo + i] = tile_hi | (key >> 32);
+    }
+    return;
+  }
 
   if (n <= kLdsItems) {
     // bitonic sort in LDS, padded to a power of two with the largest key
