@@ -27,7 +27,10 @@ namespace qr {
 constexpr int kScanThreads = 256;
 constexpr int kScanPerThread = 8;
 constexpr int kScanItems = kScanThreads * kScanPerThread;  // 2048
-constexpr int kLdsItems = 4096;                              // 32 KB of keys
+// 16 KB of keys: the kernel's whole LDS (about 21 KB) fits beside a
+// renderer's workgroups on a CU, so binning of the next views can overlap
+// rendering
+constexpr int kLdsItems = 2048;
 constexpr int kRadix = 256;
 
 // ---- device-wide exclusive scan (u32) --------------------------------------
