@@ -61,6 +61,44 @@ __device__ __forceinline__ void store_stream(float4* p, float4 v) {
   __builtin_nontemporal_store(x, reinterpret_cast<f32x4*>(p));
 }
 
+// Global-memory (address space 1) pointers. Accesses through a pointer that
+// was itself read from memory (a per-view record) compile to flat_*
+// instructions, which also count against the LDS counter and so add waits to
+// every LDS access; through these they compile to global_* instructions.
+#define QR_GLOBAL __attribute__((address_space(1)))
+
+__device__ __forceinline__ void store_stream(QR_GLOBAL float4* p, float4 v) {
+  f32x4 x = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(x, reinterpret_cast<QR_GLOBAL f32x4*>(p));
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// load_feat4 through global pointers (native vector types: HIP's vector
+// classes cannot be copied out of another address space).
+template <int DT>
+__device__ __forceinline__ float4 load_feat4_global(const QR_GLOBAL void* __restrict__ feats,
+                                                    const QR_GLOBAL float* __restrict__ scale,
+                                                    int64_t g, int dim, int d) {
+  if constexpr (DT == QR_F32) {
+    const f32x4 x = *reinterpret_cast<const QR_GLOBAL f32x4*>(
+        static_cast<const QR_GLOBAL float*>(feats) + g * dim + d);
+    return make_float4(x.x, x.y, x.z, x.w);
+  } else if constexpr (DT == QR_BF16) {
+    const u32x2 r = *reinterpret_cast<const QR_GLOBAL u32x2*>(
+        static_cast<const QR_GLOBAL uint16_t*>(feats) + g * dim + d);
+    return make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xFFFF0000u),
+                       __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xFFFF0000u));
+  } else {
+    const uint32_t r = *reinterpret_cast<const QR_GLOBAL uint32_t*>(
+        static_cast<const QR_GLOBAL uint8_t*>(feats) + g * dim + d);
+    const float s = scale[g];
+    return make_float4(e4m3_to_f32(r & 0xFFu) * s, e4m3_to_f32((r >> 8) & 0xFFu) * s,
+                       e4m3_to_f32((r >> 16) & 0xFFu) * s, e4m3_to_f32(r >> 24) * s);
+  }
+}
+
 // Host-side validation shared by the render entry points.
 inline int validate_render(const char* name, int32_t width, int32_t height, const qr_params* prm,
                            const uint32_t* tile_offsets, const uint32_t* sorted_gid,

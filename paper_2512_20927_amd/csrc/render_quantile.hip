@@ -63,6 +63,29 @@ struct ViewArgs {
   int32_t* __restrict__ n_sel;
 };
 
+// The same view with global-memory pointers (see QR_GLOBAL), as the tile
+// code uses it.
+struct GView {
+  int W, H;
+  const QR_GLOBAL uint32_t* __restrict__ tile_offsets;
+  const QR_GLOBAL uint32_t* __restrict__ sorted_gid;
+  const QR_GLOBAL f32x2* __restrict__ means2d;
+  const QR_GLOBAL f32x4* __restrict__ conic_opacity;
+  const QR_GLOBAL void* __restrict__ feats;
+  const QR_GLOBAL float* __restrict__ scale;
+  QR_GLOBAL float* __restrict__ out;
+  QR_GLOBAL float* __restrict__ T_q;
+  QR_GLOBAL int32_t* __restrict__ n_sel;
+};
+
+__device__ __forceinline__ GView to_global(const ViewArgs& v) {
+  return GView{v.W, v.H,
+               (const QR_GLOBAL uint32_t*)v.tile_offsets, (const QR_GLOBAL uint32_t*)v.sorted_gid,
+               (const QR_GLOBAL f32x2*)v.means2d, (const QR_GLOBAL f32x4*)v.conic_opacity,
+               (const QR_GLOBAL void*)v.feats, (const QR_GLOBAL float*)v.scale,
+               (QR_GLOBAL float*)v.out, (QR_GLOBAL float*)v.T_q, (QR_GLOBAL int32_t*)v.n_sel};
+}
+
 // Orders this wave's LDS writes before its later LDS reads (all lanes).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -75,7 +98,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // requested for both columns before any is used. Rows past the end repeat
 // the last one with zero weight, so the loads are unconditional.
 template <int DT>
-__device__ __forceinline__ void gather_group_merged(const ViewArgs& v, const QuantileLds& L, int grp,
+__device__ __forceinline__ void gather_group_merged(const GView& v, const QuantileLds& L, int grp,
                                                     int nu, int tx, int ty, int lane, int dim) {
   constexpr int kEB = QR_GATHER_ROWS;
   const int dim4 = dim >> 2;
@@ -96,8 +119,8 @@ __device__ __forceinline__ void gather_group_merged(const ViewArgs& v, const Qua
 #pragma unroll
       for (int e = 0; e < kEB; ++e) {
         const int g = __builtin_amdgcn_readfirstlane(ug[min(e0 + e, nu - 1)]);
-        f0[e] = load_feat4<DT>(v.feats, v.scale, g, dim, 4 * l0);
-        f1[e] = load_feat4<DT>(v.feats, v.scale, g, dim, 4 * l1);
+        f0[e] = load_feat4_global<DT>(v.feats, v.scale, g, dim, 4 * l0);
+        f1[e] = load_feat4_global<DT>(v.feats, v.scale, g, dim, 4 * l1);
       }
 #pragma unroll
       for (int e = 0; e < kEB; ++e) {
@@ -121,7 +144,7 @@ __device__ __forceinline__ void gather_group_merged(const ViewArgs& v, const Qua
       const int p = p0 + q;
       if (L.ns[p] < 0) continue;  // outside the image
       const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
-      float4* dst = reinterpret_cast<float4*>(v.out + (static_cast<int64_t>(gy) * v.W + gx) * dim);
+      QR_GLOBAL float4* dst = reinterpret_cast<QR_GLOBAL float4*>(v.out + (static_cast<int64_t>(gy) * v.W + gx) * dim);
       const float inv = L.inv[p];
       if (c0 < dim4) store_stream(dst + c0, make_float4(a0[q].x * inv, a0[q].y * inv, a0[q].z * inv, a0[q].w * inv));
       if (c1 < dim4) store_stream(dst + c1, make_float4(a1[q].x * inv, a1[q].y * inv, a1[q].z * inv, a1[q].w * inv));
@@ -132,7 +155,7 @@ __device__ __forceinline__ void gather_group_merged(const ViewArgs& v, const Qua
 // Gather-blend of a group with more than kUCap distinct selections: pixel
 // by pixel, each selection's row loaded for its own pixel.
 template <int DT>
-__device__ __forceinline__ void gather_group_per_pixel(const ViewArgs& v, const QuantileLds& L,
+__device__ __forceinline__ void gather_group_per_pixel(const GView& v, const QuantileLds& L,
                                                        const int* __restrict__ s_sel_pos,
                                                        const float* __restrict__ s_sel_w, int KP,
                                                        int grp, int tx, int ty, int lane, int dim) {
@@ -160,7 +183,7 @@ __device__ __forceinline__ void gather_group_per_pixel(const ViewArgs& v, const 
         const bool ok = j < n[q];
         const int g = ok ? static_cast<int>(v.sorted_gid[s_sel_pos[(p0 + q) * KP + j]]) : safe;
         w[q] = ok ? s_sel_w[(p0 + q) * KP + j] : 0.f;
-        f[q] = load_feat4<DT>(v.feats, v.scale, g, dim, 4 * c);
+        f[q] = load_feat4_global<DT>(v.feats, v.scale, g, dim, 4 * c);
       }
 #pragma unroll
       for (int q = 0; q < kPG; ++q) {
@@ -175,7 +198,7 @@ __device__ __forceinline__ void gather_group_per_pixel(const ViewArgs& v, const 
       if (n[q] < 0) continue;  // outside the image
       const int p = p0 + q;
       const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
-      float4* dst = reinterpret_cast<float4*>(v.out + (static_cast<int64_t>(gy) * v.W + gx) * dim);
+      QR_GLOBAL float4* dst = reinterpret_cast<QR_GLOBAL float4*>(v.out + (static_cast<int64_t>(gy) * v.W + gx) * dim);
       const float inv = L.inv[p];
       store_stream(dst + c, make_float4(acc[q].x * inv, acc[q].y * inv, acc[q].z * inv, acc[q].w * inv));
     }
@@ -190,7 +213,7 @@ __device__ __forceinline__ void gather_group_per_pixel(const ViewArgs& v, const 
 // Shared LDS (the record batch) is only rewritten after a barrier that every
 // wave reaches once it has finished the previous tile.
 template <int DT>
-__device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K, int dim,
+__device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, int dim,
                                               const qr_params& prm, QuantileLds& L,
                                               int* __restrict__ s_sel_gid,
                                               float* __restrict__ s_sel_w,
@@ -226,8 +249,10 @@ __device__ __forceinline__ void quantile_tile(const ViewArgs& v, int tile, int K
     const int idx = batch + tid;
     if (idx < hi) {
       const int g = static_cast<int>(v.sorted_gid[idx]);
-      L.mean[tid] = v.means2d[g];
-      L.co[tid] = v.conic_opacity[g];
+      const f32x2 m = v.means2d[g];
+      const f32x4 c = v.conic_opacity[g];
+      L.mean[tid] = make_float2(m.x, m.y);
+      L.co[tid] = make_float4(c.x, c.y, c.z, c.w);
     } else {  // padding record: opacity 0 is below alpha_min on every ray
       L.mean[tid] = make_float2(0.f, 0.f);
       L.co[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -358,8 +383,8 @@ render_quantile_kernel(ViewArgs v, int n_tiles, qr_params prm, int K, int dim,
   __shared__ QuantileLds L;
   int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);                            // [256][KP]
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);  // [256][KP]
-  quantile_tile<DT>(v, xcd_remap(blockIdx.x, n_tiles), K, dim, prm, L, s_sel_gid, s_sel_w,
-                    sel_gid_out, sel_w_out);
+  quantile_tile<DT>(to_global(v), xcd_remap(blockIdx.x, n_tiles), K, dim, prm, L, s_sel_gid,
+                    s_sel_w, sel_gid_out, sel_w_out);
 }
 
 __device__ __forceinline__ ViewArgs view_args(const qr_view& qv) {
@@ -392,7 +417,7 @@ render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t
     const uint32_t item = __builtin_amdgcn_readfirstlane(s_item[it]);
     if (item >= n_items) break;
     const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[item]);
-    const ViewArgs v = view_args(views[packed >> kViewShift]);
+    const GView v = to_global(view_args(views[packed >> kViewShift]));
     quantile_tile<DT>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
                       nullptr, nullptr);
   }
@@ -412,7 +437,7 @@ render_quantile_batched_grid_kernel(const qr_view* __restrict__ views,
   int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);
   const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[xcd_remap(blockIdx.x, n_items)]);
-  const ViewArgs v = view_args(views[packed >> kViewShift]);
+  const GView v = to_global(view_args(views[packed >> kViewShift]));
   quantile_tile<DT>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
                     nullptr, nullptr);
 }

@@ -4,6 +4,13 @@ from two counter passes.
     python paper_2512_20927_amd/profile_summary.py stats <kernel_stats.csv> [--top N]
     python paper_2512_20927_amd/profile_summary.py pmc <fetch.csv> <write.csv> --kernel NAME
         [--family NAME]
+    python paper_2512_20927_amd/profile_summary.py counters <counters.csv> --kernel NAME
+
+``counters`` prints the per-dispatch mean of every counter collected for the
+kernel, and the derived MFMA and VALU figures where their counters are present:
+MFMA busy % = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs), VALU busy %
+= SQ_ACTIVE_INST_VALU x 4 / (GRBM_GUI_ACTIVE x SIMDs) (the counter is in quad
+cycles), bf16 MFMA flops = SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512.
 
 ``pmc`` reads the counter_collection CSVs of one ``--pmc FETCH_SIZE`` and one
 ``--pmc WRITE_SIZE`` run of a command that first made a plain 1 GiB device
@@ -84,6 +91,35 @@ def pmc(fetch_csv: str, write_csv: str, kernel: str, family: str) -> str:
     ])
 
 
+N_SIMD = 256 * 4  # MI355X: 256 CUs of 4 SIMDs
+
+
+def counters(path: str, kernel: str) -> str:
+    rows = [r for r in csv.DictReader(open(path)) if kernel in r["Kernel_Name"]]
+    if not rows:
+        raise SystemExit("kernel %r not found" % kernel)
+    per = {}
+    durs = {}
+    for r in rows:
+        per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        durs[r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    mean = {k: sum(v) / len(v) for k, v in per.items()}
+    out = ["kernel: %s" % kernel, "dispatches: %d" % len(durs),
+           "mean_duration_ms_under_counters: %.4f" % (1e3 * sum(durs.values()) / len(durs))]
+    for k in sorted(mean):
+        out.append("%s_per_dispatch: %.1f" % (k, mean[k]))
+    gui = mean.get("GRBM_GUI_ACTIVE")
+    if gui:
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in mean:
+            out.append("mfma_busy_pct: %.1f" % (100.0 * mean["SQ_VALU_MFMA_BUSY_CYCLES"] / (gui * N_SIMD)))
+        if "SQ_ACTIVE_INST_VALU" in mean:
+            out.append("valu_busy_pct: %.1f" % (100.0 * 4.0 * mean["SQ_ACTIVE_INST_VALU"] / (gui * N_SIMD)))
+    if "SQ_INSTS_VALU_MFMA_MOPS_BF16" in mean:
+        flops = mean["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * 512.0
+        out.append("bf16_mfma_flops_per_dispatch: %.4g" % flops)
+    return "\n".join(out)
+
+
 def read_summary(path: str) -> dict:
     """key: value lines of a summary file (other lines ignored)."""
     out = {}
@@ -107,11 +143,16 @@ def main():
     b.add_argument("write_csv")
     b.add_argument("--kernel", required=True)
     b.add_argument("--family", default="render_quantile", choices=sorted(KERNEL_SOURCES))
+    c = sub.add_parser("counters")
+    c.add_argument("csv")
+    c.add_argument("--kernel", required=True)
     args = ap.parse_args()
     if args.cmd == "stats":
         print(stats(args.csv, args.top))
-    else:
+    elif args.cmd == "pmc":
         print(pmc(args.fetch_csv, args.write_csv, args.kernel, args.family))
+    else:
+        print(counters(args.csv, args.kernel))
 
 
 if __name__ == "__main__":
