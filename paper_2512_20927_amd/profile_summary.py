@@ -7,9 +7,11 @@ from two counter passes.
     python paper_2512_20927_amd/profile_summary.py counters <counters.csv> --kernel NAME
 
 ``counters`` prints the per-dispatch mean of every counter collected for the
-kernel, and the derived MFMA and VALU figures where their counters are present:
-MFMA busy % = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs), VALU busy %
-= SQ_ACTIVE_INST_VALU x 4 / (GRBM_GUI_ACTIVE x SIMDs) (the counter is in quad
+kernel, and the derived MFMA and VALU figures where their counters are present.
+The collected values are sums over all counter instances; GRBM_GUI_ACTIVE is
+therefore the busy cycles of one XCD times 8, and the derived figures use
+G = GRBM_GUI_ACTIVE / 8: MFMA busy % = SQ_VALU_MFMA_BUSY_CYCLES / (G x SIMDs),
+VALU busy % = SQ_ACTIVE_INST_VALU x 4 / (G x SIMDs) (the counter is in quad
 cycles), bf16 MFMA flops = SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512.
 
 ``pmc`` reads the counter_collection CSVs of one ``--pmc FETCH_SIZE`` and one
@@ -92,6 +94,7 @@ def pmc(fetch_csv: str, write_csv: str, kernel: str, family: str) -> str:
 
 
 N_SIMD = 256 * 4  # MI355X: 256 CUs of 4 SIMDs
+N_XCD = 8
 
 
 def counters(path: str, kernel: str) -> str:
@@ -110,6 +113,7 @@ def counters(path: str, kernel: str) -> str:
         out.append("%s_per_dispatch: %.1f" % (k, mean[k]))
     gui = mean.get("GRBM_GUI_ACTIVE")
     if gui:
+        gui /= N_XCD
         if "SQ_VALU_MFMA_BUSY_CYCLES" in mean:
             out.append("mfma_busy_pct: %.1f" % (100.0 * mean["SQ_VALU_MFMA_BUSY_CYCLES"] / (gui * N_SIMD)))
         if "SQ_ACTIVE_INST_VALU" in mean:
@@ -117,6 +121,10 @@ def counters(path: str, kernel: str) -> str:
     if "SQ_INSTS_VALU_MFMA_MOPS_BF16" in mean:
         flops = mean["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * 512.0
         out.append("bf16_mfma_flops_per_dispatch: %.4g" % flops)
+        if gui:
+            secs = gui / 2.4e9
+            out.append("bf16_mfma_tflops_over_busy_time: %.1f  (GRBM_GUI_ACTIVE / 8 at 2.4 GHz)"
+                       % (flops / secs / 1e12))
     return "\n".join(out)
 
 
