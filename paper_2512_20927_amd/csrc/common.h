@@ -26,21 +26,14 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
   return __uint_as_float(static_cast<uint32_t>(h) << 16);
 }
 
-// OCP e4m3 code -> float32, from the format definition: bias 7, three
-// mantissa bits, subnormals at exponent 0. The 7-bit magnitude is placed in
-// the float32 exponent/mantissa fields and rebiased by a multiply by 2^120;
-// the subnormal case is handled explicitly so that no float32 denormal is
-// ever formed. Code 0x7F/0xFF (NaN) never occurs in encoded tables.
-__device__ __forceinline__ float e4m3_to_f32(uint32_t code) {
-  const uint32_t mag = code & 0x7Fu;
-  const uint32_t e = mag >> 3;
-  float v;
-  if (e == 0) {
-    v = static_cast<float>(mag) * 0.001953125f;  // m * 2^-9
-  } else {
-    v = __uint_as_float((mag + (120u << 3)) << 20);  // (e+120) exponent, m mantissa
-  }
-  return (code & 0x80u) ? -v : v;
+// Four OCP e4m3 codes (bytes 0..3 of r, byte 0 first) to float32, times s.
+// gfx950's v_cvt_pk_f32_fp8 decodes two OCP e4m3 values (subnormals
+// included) per instruction.
+__device__ __forceinline__ float4 e4m3x4_to_f32(uint32_t r, float s) {
+  typedef float f32x2_ __attribute__((ext_vector_type(2)));
+  const f32x2_ lo = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(r), false);
+  const f32x2_ hi = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(r), true);
+  return make_float4(lo.x * s, lo.y * s, hi.x * s, hi.y * s);
 }
 
 // Loads 4 consecutive features (d .. d+3, d % 4 == 0) of row g as float32.
@@ -57,8 +50,7 @@ __device__ __forceinline__ float4 load_feat4(const void* __restrict__ feats,
   } else {
     const uint32_t r = *reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(feats) + g * dim + d);
     const float s = scale[g];
-    return make_float4(e4m3_to_f32(r & 0xFFu) * s, e4m3_to_f32((r >> 8) & 0xFFu) * s,
-                       e4m3_to_f32((r >> 16) & 0xFFu) * s, e4m3_to_f32(r >> 24) * s);
+    return e4m3x4_to_f32(r, s);
   }
 }
 

@@ -51,15 +51,15 @@ __device__ __forceinline__ void chain_geometry(float dL_dalpha, const AlphaEval&
 
 // Loads the [256 px x kCW] slice [c0, c0 + kCW) of the tile's grad_out into
 // LDS (rows of pixels outside the image are zero).
-__device__ __forceinline__ void load_grad_chunk(float* s_g, const float* __restrict__ grad_out,
+__device__ __forceinline__ void load_grad_chunk(float* s_g, const QR_GLOBAL float* __restrict__ grad_out,
                                                 int W, int H, int tx, int ty, int dim, int c0) {
   constexpr int per_row = kCW / 4;
   for (int e = threadIdx.x; e < kTilePix * per_row; e += kTilePix) {
     const int p = e / per_row, c4 = e - p * per_row;
     const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
     if (gx < W && gy < H && c0 + 4 * c4 < dim)  // dim is a multiple of 16, not of kCW
-      v = *reinterpret_cast<const float4*>(grad_out + (static_cast<int64_t>(gy) * W + gx) * dim + c0 + 4 * c4);
+      v = *reinterpret_cast<const QR_GLOBAL f32x4*>(grad_out + (static_cast<int64_t>(gy) * W + gx) * dim + c0 + 4 * c4);
     float* r = s_g + p * kGStride + 4 * c4;
     r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
   }
@@ -88,6 +88,9 @@ quantile_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm, 
                          const float* __restrict__ grad_out, float* __restrict__ grad_features,
                          float* __restrict__ grad_means2d, float* __restrict__ grad_co) {
   extern __shared__ unsigned char lds[];
+  const QR_GLOBAL void* gfeats = (const QR_GLOBAL void*)feats;
+  const QR_GLOBAL float* gscale = (const QR_GLOBAL float*)scale;
+  const QR_GLOBAL float* ggrad = (const QR_GLOBAL float*)grad_out;
   // persistent arrays
   int* s_pos = reinterpret_cast<int*>(lds);                          // [256][KM]
   float* s_w = reinterpret_cast<float*>(s_pos + kTilePix * KM);     // [256][KM]
@@ -101,9 +104,11 @@ quantile_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm, 
   int* s_ugid = s_upos + kWin;                                       // [kWin]
   uint32_t* s_misc = reinterpret_cast<uint32_t*>(s_ugid + kWin);     // [8]
   float* s_thr = reinterpret_cast<float*>(s_misc + 8);               // [QR_MAX_K + 1]
-  // phase-scoped union
-  unsigned char* u = reinterpret_cast<unsigned char*>(s_thr + QR_MAX_K + 1);
-  u = reinterpret_cast<unsigned char*>((reinterpret_cast<uintptr_t>(u) + 15) & ~uintptr_t(15));
+  // phase-scoped union, 16-byte aligned (offset fixed at compile time, so
+  // every access keeps the LDS address space)
+  constexpr size_t kPersistBytes = static_cast<size_t>(kTilePix) * KM * (4 + 4 + 4 + 2) +
+                                   kTilePix * 8 + kWin * 16 + 8 * 4 + (QR_MAX_K + 1) * 4;
+  unsigned char* u = lds + ((kPersistBytes + 15) & ~static_cast<size_t>(15));
   float4* s_co = reinterpret_cast<float4*>(u);                       // A: [256]
   float2* s_mean = reinterpret_cast<float2*>(s_co + kTilePix);       // A: [256]
   int* s_bgid = reinterpret_cast<int*>(s_mean + kTilePix);           // A: [256]
@@ -198,7 +203,7 @@ quantile_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm, 
     __syncthreads();
 
     for (int c0 = 0; c0 < dim; c0 += kCW) {
-      load_grad_chunk(s_g, grad_out, W, H, tx, ty, dim, c0);
+      load_grad_chunk(s_g, ggrad, W, H, tx, ty, dim, c0);
       __syncthreads();
       if (w0 == 0) {
         // dots d_pj over this chunk, for all of this pixel's selections
@@ -211,7 +216,7 @@ quantile_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm, 
 #pragma unroll
             for (int c4 = 0; c4 < kCW / 4; ++c4) {
               if (c0 + 4 * c4 >= dim) break;
-              const float4 f = load_feat4<DT>(feats, scale, g, dim, c0 + 4 * c4);
+              const float4 f = load_feat4_global<DT>(gfeats, gscale, g, dim, c0 + 4 * c4);
               acc += gr[4 * c4] * f.x + gr[4 * c4 + 1] * f.y + gr[4 * c4 + 2] * f.z + gr[4 * c4 + 3] * f.w;
             }
             d[j] += acc;
@@ -289,6 +294,9 @@ dense_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
                       const float* __restrict__ scale, int dim, const float* __restrict__ out,
                       const float* __restrict__ grad_out, float* __restrict__ grad_features,
                       float* __restrict__ grad_means2d, float* __restrict__ grad_co) {
+  const QR_GLOBAL void* gfeats = (const QR_GLOBAL void*)feats;
+  const QR_GLOBAL float* gscale = (const QR_GLOBAL float*)scale;
+  const QR_GLOBAL float* ggrad = (const QR_GLOBAL float*)grad_out;
   __shared__ float s_g[kTilePix * kGStride];
   __shared__ float s_f[kDB * kCW];
   __shared__ float s_w[kDB][kTilePix + 1];  // +1: entries land in distinct banks
@@ -318,8 +326,8 @@ dense_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
     if (gx < W && gy < H) {
       const int64_t base = (static_cast<int64_t>(gy) * W + gx) * dim;
       for (int c = lane * 4; c < dim; c += 256) {
-        const float4 a = *reinterpret_cast<const float4*>(grad_out + base + c);
-        const float4 b = *reinterpret_cast<const float4*>(out + base + c);
+        const f32x4 a = *reinterpret_cast<const QR_GLOBAL f32x4*>(ggrad + base + c);
+        const f32x4 b = *reinterpret_cast<const QR_GLOBAL f32x4*>((const QR_GLOBAL float*)out + base + c);
         acc += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
       }
     }
@@ -364,11 +372,11 @@ dense_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
     for (int j = 0; j < kDB; ++j) d[j] = 0.f;
     for (int c0 = 0; c0 < dim; c0 += kCW) {
       __syncthreads();
-      load_grad_chunk(s_g, grad_out, W, H, tx, ty, dim, c0);
+      load_grad_chunk(s_g, ggrad, W, H, tx, ty, dim, c0);
       for (int e = tid; e < kDB * (kCW / 4); e += kTilePix) {
         const int j = e / (kCW / 4), c4 = e - j * (kCW / 4);
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (j < cnt && c0 + 4 * c4 < dim) v = load_feat4<DT>(feats, scale, s_gid[j], dim, c0 + 4 * c4);
+        if (j < cnt && c0 + 4 * c4 < dim) v = load_feat4_global<DT>(gfeats, gscale, s_gid[j], dim, c0 + 4 * c4);
         *reinterpret_cast<float4*>(&s_f[j * kCW + 4 * c4]) = v;
       }
       __syncthreads();

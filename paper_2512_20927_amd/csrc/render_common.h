@@ -94,8 +94,7 @@ __device__ __forceinline__ float4 load_feat4_global(const QR_GLOBAL void* __rest
     const uint32_t r = *reinterpret_cast<const QR_GLOBAL uint32_t*>(
         static_cast<const QR_GLOBAL uint8_t*>(feats) + g * dim + d);
     const float s = scale[g];
-    return make_float4(e4m3_to_f32(r & 0xFFu) * s, e4m3_to_f32((r >> 8) & 0xFFu) * s,
-                       e4m3_to_f32((r >> 16) & 0xFFu) * s, e4m3_to_f32(r >> 24) * s);
+    return e4m3x4_to_f32(r, s);
   }
 }
 

@@ -262,6 +262,45 @@ def test_render_parity_room_full_size_sampled_tiles(qr, room_res):
     assert np.all(np.isfinite(q["out"])) and np.all(np.isfinite(d["out"]))
 
 
+@pytest.mark.parametrize("scale", [1.0, 0.3711])
+def test_fp8_decode_of_every_code(qr, scale):
+    """One Gaussian whose feature row holds every finite e4m3 code (all but
+    0x7F and 0xFF). A pixel that selects only this Gaussian has
+    out = (alpha f) / alpha = f, so Q-Render and the dense blend must
+    return the decoded row times the scale: each code's value against the
+    format definition (oracle table), byte order in the 4-byte loads
+    included."""
+    codes = np.array([c for c in range(256) if c not in (0x7F, 0xFF)] + [0, 0], np.uint8)
+    sc = synth.Scene(np.zeros((1, 3), np.float32), np.full((1, 3), 0.3, np.float32),
+                     np.float32([[1, 0, 0, 0]]), np.float32([0.9]), np.zeros((1, 256), np.float32))
+    cam = synth.tiny_camera(32)
+    pr = qr.project(_t(sc.means), _t(sc.scales), _t(sc.quats), _t(sc.opacity), cam)
+    bins = qr.bin_sort(pr, 32, 32)
+    feats = _t(codes[None, :])
+    sc_t = torch.tensor([scale], dtype=torch.float32, device="cuda")
+    q = qr.render_quantile(pr, bins, feats, 32, 32, 8, feature_scale=sc_t)
+    d = qr.render_dense(pr, bins, feats, 32, 32, feature_scale=sc_t)
+    torch.cuda.synchronize()
+    want = oracle.quant.e4m3_decode(codes) * np.float64(np.float32(scale))
+    nz = want != 0
+    assert int(q["n_sel"][16, 16].item()) == 1
+
+    def check(got, spread):
+        # every code decoded exactly: got = want * (common factor), up to the
+        # roundings of the products that follow the decode
+        assert np.all(got[~nz] == 0)
+        ratio = got[nz] / want[nz]
+        assert np.ptp(ratio) <= spread * np.abs(ratio).max(), np.ptp(ratio)
+        assert abs(ratio.mean() - 1.0) < 1e-4
+
+    # Q-Render: float32 scale, weight and normalisation products
+    check(q["out"][16, 16].cpu().numpy().astype(np.float64), 6e-7)
+    # dense: out = alpha f with T_final = 1 - alpha; its bf16 hi/lo split
+    # product is exact to below 2^-16 relative
+    alpha = 1.0 - float(d["T_final"][16, 16].item())
+    check(d["out"][16, 16].cpu().numpy().astype(np.float64) / alpha, 2.0 ** -15)
+
+
 @pytest.mark.parametrize("storage", ["bf16", "fp8"])
 def test_quantized_storage(qr, storage):
     """Storage codes are bit-exact with the oracle's encoder; the kernels on
