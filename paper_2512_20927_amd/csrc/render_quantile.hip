@@ -11,11 +11,13 @@
 // Phase 2 (gather-blend): pixels are gathered four at a time (a row segment
 // of the tile) with the lanes of a wave spanning the feature dimension. The
 // four pixels' selection lists are first merged into their distinct
-// selections, each carrying the four weights, so every distinct feature row
-// is loaded once per group (mostly from L2: neighbouring pixels select the
-// same Gaussians); rows are accumulated in float32, scaled by 1 / (1 - T^Q)
-// and streamed to the [H, W, D] map with non-temporal stores. The map write
-// is the dominant HBM traffic of the whole pipeline.
+// selections, each carrying the four weights already divided by the pixel's
+// 1 - T^Q, so every distinct feature row is loaded once per group (mostly
+// from L2: neighbouring pixels select the same Gaussians); rows are
+// accumulated in float32 and streamed to the [H, W, D] map with non-temporal
+// stores. The map write is the dominant HBM traffic of the whole pipeline.
+// Everything after the walk is wave-local: wave w's pixels (tile rows
+// 4w .. 4w+3) are exactly the pixels of the groups it gathers.
 #include "common.h"
 #include "render_common.h"
 
@@ -32,9 +34,6 @@ constexpr int kGroups = kTilePix / kPG;    // 64 pixel groups per tile
 #define QR_UCAP 16
 #endif
 constexpr int kUCap = QR_UCAP;             // distinct selections kept per group
-#ifndef QR_GATHER_ROWS
-#define QR_GATHER_ROWS 4                   // distinct rows requested together in the gather
-#endif
 // Three 45 KB workgroups fill a CU's LDS: registers are bounded to match
 // (three waves per SIMD).
 constexpr int kWavesPerSimd = 3;
@@ -92,15 +91,45 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// R distinct rows of a merged group, both column slots of the lane: all 2R
+// loads are requested before the first is used, then accumulated in row order.
+template <int DT, int R>
+__device__ __forceinline__ void accum_rows(const GView& v, const int* ug, const float4* uw, int e0,
+                                           int l0, int l1, int dim, float4 (&a0)[kPG],
+                                           float4 (&a1)[kPG]) {
+  float4 f0[R], f1[R];
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    const int g = __builtin_amdgcn_readfirstlane(ug[e0 + e]);
+    f0[e] = load_feat4_global<DT>(v.feats, v.scale, g, dim, 4 * l0);
+    f1[e] = load_feat4_global<DT>(v.feats, v.scale, g, dim, 4 * l1);
+  }
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    const float4 w = uw[e0 + e];
+    const float ws[kPG] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int q = 0; q < kPG; ++q) {
+      a0[q].x += ws[q] * f0[e].x;
+      a0[q].y += ws[q] * f0[e].y;
+      a0[q].z += ws[q] * f0[e].z;
+      a0[q].w += ws[q] * f0[e].w;
+      a1[q].x += ws[q] * f1[e].x;
+      a1[q].y += ws[q] * f1[e].y;
+      a1[q].z += ws[q] * f1[e].z;
+      a1[q].w += ws[q] * f1[e].w;
+    }
+  }
+}
+
 // Gather-blend of one 4-pixel group whose distinct selections are merged:
-// out[p] = (sum_e w_pe f_e) / (1 - T^Q_p). Each lane owns two float4 columns
-// per pass (512 features per pass for the wave); kEB distinct rows are
-// requested for both columns before any is used. Rows past the end repeat
-// the last one with zero weight, so the loads are unconditional.
+// out[p] = sum_e (w_pe / (1 - T^Q_p)) f_e (the normalisation is folded into
+// the merged weights). Each lane owns two float4 columns per pass (512
+// features per pass for the wave); rows are taken four at a time, the last
+// two or one on their own, so no multiply is spent on padding.
 template <int DT>
 __device__ __forceinline__ void gather_group_merged(const GView& v, const QuantileLds& L, int grp,
                                                     int nu, int tx, int ty, int lane, int dim) {
-  constexpr int kEB = QR_GATHER_ROWS;
   const int dim4 = dim >> 2;
   const int p0 = grp * kPG;
   const int* ug = &L.ugid[grp * kUCap];
@@ -114,40 +143,21 @@ __device__ __forceinline__ void gather_group_merged(const GView& v, const Quanti
       a0[q] = make_float4(0.f, 0.f, 0.f, 0.f);
       a1[q] = a0[q];
     }
-    for (int e0 = 0; e0 < nu; e0 += kEB) {
-      float4 f0[kEB], f1[kEB];
-#pragma unroll
-      for (int e = 0; e < kEB; ++e) {
-        const int g = __builtin_amdgcn_readfirstlane(ug[min(e0 + e, nu - 1)]);
-        f0[e] = load_feat4_global<DT>(v.feats, v.scale, g, dim, 4 * l0);
-        f1[e] = load_feat4_global<DT>(v.feats, v.scale, g, dim, 4 * l1);
-      }
-#pragma unroll
-      for (int e = 0; e < kEB; ++e) {
-        const float4 w = e0 + e < nu ? uw[e0 + e] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float ws[kPG] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-        for (int q = 0; q < kPG; ++q) {
-          a0[q].x += ws[q] * f0[e].x;
-          a0[q].y += ws[q] * f0[e].y;
-          a0[q].z += ws[q] * f0[e].z;
-          a0[q].w += ws[q] * f0[e].w;
-          a1[q].x += ws[q] * f1[e].x;
-          a1[q].y += ws[q] * f1[e].y;
-          a1[q].z += ws[q] * f1[e].z;
-          a1[q].w += ws[q] * f1[e].w;
-        }
-      }
+    int e0 = 0;
+    for (; e0 + 4 <= nu; e0 += 4) accum_rows<DT, 4>(v, ug, uw, e0, l0, l1, dim, a0, a1);
+    if (e0 + 2 <= nu) {
+      accum_rows<DT, 2>(v, ug, uw, e0, l0, l1, dim, a0, a1);
+      e0 += 2;
     }
+    if (e0 < nu) accum_rows<DT, 1>(v, ug, uw, e0, l0, l1, dim, a0, a1);
 #pragma unroll
     for (int q = 0; q < kPG; ++q) {
       const int p = p0 + q;
       if (L.ns[p] < 0) continue;  // outside the image
       const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
       QR_GLOBAL float4* dst = reinterpret_cast<QR_GLOBAL float4*>(v.out + (static_cast<int64_t>(gy) * v.W + gx) * dim);
-      const float inv = L.inv[p];
-      if (c0 < dim4) store_stream(dst + c0, make_float4(a0[q].x * inv, a0[q].y * inv, a0[q].z * inv, a0[q].w * inv));
-      if (c1 < dim4) store_stream(dst + c1, make_float4(a1[q].x * inv, a1[q].y * inv, a1[q].z * inv, a1[q].w * inv));
+      if (c0 < dim4) store_stream(dst + c0, a0[q]);
+      if (c1 < dim4) store_stream(dst + c1, a1[q]);
     }
   }
 }
@@ -306,14 +316,16 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
     const int grp = wave * kWaveGroups + lane;
     const int p0 = grp * kPG;
     // each pixel's next selection (list position and weight) kept in registers
+    // (weights are stored already divided by the pixel's 1 - T^Q)
     int n[kPG], idx[kPG], head[kPG];
-    float hw[kPG];
+    float hw[kPG], inv[kPG];
 #pragma unroll
     for (int q = 0; q < kPG; ++q) {
       n[q] = max(L.ns[p0 + q], 0);
+      inv[q] = L.inv[p0 + q];
       idx[q] = 0;
       head[q] = n[q] > 0 ? s_sel_pos[(p0 + q) * KP] : 0x7fffffff;
-      hw[q] = n[q] > 0 ? s_sel_w[(p0 + q) * KP] : 0.f;
+      hw[q] = n[q] > 0 ? s_sel_w[(p0 + q) * KP] * inv[q] : 0.f;
     }
     int cnt = 0;
     for (;;) {
@@ -331,7 +343,7 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
           wq[q] = hw[q];
           ++idx[q];
           head[q] = idx[q] < n[q] ? s_sel_pos[(p0 + q) * KP + idx[q]] : 0x7fffffff;
-          hw[q] = idx[q] < n[q] ? s_sel_w[(p0 + q) * KP + idx[q]] : 0.f;
+          hw[q] = idx[q] < n[q] ? s_sel_w[(p0 + q) * KP + idx[q]] * inv[q] : 0.f;
         }
       }
       L.ugid[grp * kUCap + cnt] = best;  // position for now
