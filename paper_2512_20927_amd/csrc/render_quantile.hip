@@ -47,6 +47,7 @@ struct QuantileLds {
   int unum[kGroups];                       // distinct entries per group, -1 if over kUCap
   int ugid[kGroups * kUCap];               // a group's distinct selections (list positions until converted)
   float4 uw[kGroups * kUCap];              // their weights for the group's four pixels, x = first pixel
+  uint8_t umask[kGroups * kUCap];          // bit q: pixel q of the group selected the entry
 };
 
 struct ViewArgs {
@@ -94,9 +95,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // R distinct rows of a merged group, both column slots of the lane: all 2R
 // loads are requested before the first is used, then accumulated in row order.
 template <int DT, int R>
-__device__ __forceinline__ void accum_rows(const GView& v, const int* ug, const float4* uw, int e0,
-                                           int l0, int l1, int dim, float4 (&a0)[kPG],
-                                           float4 (&a1)[kPG]) {
+__device__ __forceinline__ void accum_rows(const GView& v, const int* ug, const float4* uw,
+                                           const uint8_t* um, int e0, int l0, int l1, int dim,
+                                           float4 (&a0)[kPG], float4 (&a1)[kPG]) {
   float4 f0[R], f1[R];
 #pragma unroll
   for (int e = 0; e < R; ++e) {
@@ -108,8 +109,12 @@ __device__ __forceinline__ void accum_rows(const GView& v, const int* ug, const 
   for (int e = 0; e < R; ++e) {
     const float4 w = uw[e0 + e];
     const float ws[kPG] = {w.x, w.y, w.z, w.w};
+    // pixels that did not select the row have weight 0: skipped by uniform
+    // (scalar) branches instead of multiplied
+    const uint32_t mk = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(um[e0 + e]));
 #pragma unroll
     for (int q = 0; q < kPG; ++q) {
+      if (!(mk & (1u << q))) continue;
       a0[q].x += ws[q] * f0[e].x;
       a0[q].y += ws[q] * f0[e].y;
       a0[q].z += ws[q] * f0[e].z;
@@ -134,6 +139,7 @@ __device__ __forceinline__ void gather_group_merged(const GView& v, const Quanti
   const int p0 = grp * kPG;
   const int* ug = &L.ugid[grp * kUCap];
   const float4* uw = &L.uw[grp * kUCap];
+  const uint8_t* um = &L.umask[grp * kUCap];
   for (int cb = 0; cb < dim4; cb += 128) {
     const int c0 = cb + lane, c1 = cb + 64 + lane;
     const int l0 = min(c0, dim4 - 1), l1 = min(c1, dim4 - 1);  // in-bounds columns to load
@@ -144,12 +150,12 @@ __device__ __forceinline__ void gather_group_merged(const GView& v, const Quanti
       a1[q] = a0[q];
     }
     int e0 = 0;
-    for (; e0 + 4 <= nu; e0 += 4) accum_rows<DT, 4>(v, ug, uw, e0, l0, l1, dim, a0, a1);
+    for (; e0 + 4 <= nu; e0 += 4) accum_rows<DT, 4>(v, ug, uw, um, e0, l0, l1, dim, a0, a1);
     if (e0 + 2 <= nu) {
-      accum_rows<DT, 2>(v, ug, uw, e0, l0, l1, dim, a0, a1);
+      accum_rows<DT, 2>(v, ug, uw, um, e0, l0, l1, dim, a0, a1);
       e0 += 2;
     }
-    if (e0 < nu) accum_rows<DT, 1>(v, ug, uw, e0, l0, l1, dim, a0, a1);
+    if (e0 < nu) accum_rows<DT, 1>(v, ug, uw, um, e0, l0, l1, dim, a0, a1);
 #pragma unroll
     for (int q = 0; q < kPG; ++q) {
       const int p = p0 + q;
@@ -336,11 +342,13 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
         break;
       }
       float wq[kPG];
+      uint32_t mk = 0u;
 #pragma unroll
       for (int q = 0; q < kPG; ++q) {
         wq[q] = 0.f;
         if (head[q] == best) {
           wq[q] = hw[q];
+          mk |= 1u << q;
           ++idx[q];
           head[q] = idx[q] < n[q] ? s_sel_pos[(p0 + q) * KP + idx[q]] : 0x7fffffff;
           hw[q] = idx[q] < n[q] ? s_sel_w[(p0 + q) * KP + idx[q]] * inv[q] : 0.f;
@@ -348,6 +356,7 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
       }
       L.ugid[grp * kUCap + cnt] = best;  // position for now
       L.uw[grp * kUCap + cnt] = make_float4(wq[0], wq[1], wq[2], wq[3]);
+      L.umask[grp * kUCap + cnt] = static_cast<uint8_t>(mk);
       ++cnt;
     }
     L.unum[grp] = cnt;
