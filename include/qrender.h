@@ -272,10 +272,11 @@ int qr_render_quantile(void* stream, int32_t width, int32_t height,
  *     in contiguous runs of the schedule, and workgroups retire as they
  *     finish (work on other streams can interleave). `workspace` is unused
  *     and may be NULL.
- *   n_workgroups > 0: that many persistent workgroups take items in schedule
- *     order through an atomic counter held in `workspace` (device, >= 4
- *     bytes), which the call resets; the schedule decides load balance (e.g.
- *     the longest tile lists first).
+ *   n_workgroups > 0: that many persistent workgroups take items through
+ *     atomic counters held in `workspace` (device, >= 32 bytes), which the
+ *     call resets: the schedule is cut into eight contiguous ranges, one per
+ *     XCD, each taken in order by the workgroups of its XCD first and by the
+ *     others once their own range is used up.
  * Errors: QR_ERR_INVALID_ARG for null pointers, counts out of range or
  * n_workgroups < 0; QR_ERR_CAPACITY for a missing or short workspace in
  * persistent mode; QR_ERR_UNSUPPORTED for K, dtype or dim outside the limits.

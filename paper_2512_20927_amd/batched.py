@@ -47,7 +47,7 @@ class BatchedQuantile:
         self.natural = torch.tensor(nat, dtype=torch.int64, device=dev).to(torch.int32)
         self.heavy = torch.empty(self.n_items, dtype=torch.int32, device=dev)
         self.sched_ws = torch.empty(64, dtype=torch.int32, device=dev)
-        self.counter = torch.empty(1, dtype=torch.int32, device=dev)
+        self.counter = torch.empty(8, dtype=torch.int32, device=dev)  # one work counter per XCD
         props = torch.cuda.get_device_properties(dev)
         self.n_cu = props.multi_processor_count
         self.device_name = props.name

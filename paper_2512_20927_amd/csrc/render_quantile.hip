@@ -415,9 +415,18 @@ __device__ __forceinline__ ViewArgs view_args(const qr_view& qv) {
                   qv.feature_scale, qv.out, qv.T_q, qv.n_sel};
 }
 
-// Many views in one persistent launch. Workgroups take (view, tile) items
-// from `schedule` in order through an atomic counter until it is exhausted;
-// every workgroup leaves once the counter passes n_items.
+// Many views in one persistent launch. The schedule is cut into one
+// contiguous range per XCD (workgroup b runs on XCD b % 8), each with its own
+// atomic counter: a workgroup takes items of its XCD's range in order, so the
+// tiles in flight on an XCD are neighbours whose records and feature rows
+// share that XCD's L2; once its range is used up it takes items from the
+// other ranges, and it leaves when every range is used up.
+constexpr int kXcdQueues = 8;
+
+__device__ __forceinline__ uint32_t queue_begin(int64_t n_items, int q) {
+  return static_cast<uint32_t>(n_items * q / kXcdQueues);
+}
+
 template <int DT>
 __global__ void __launch_bounds__(kTilePix, kWavesPerSimd)
 render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t* __restrict__ schedule,
@@ -431,8 +440,22 @@ render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t
   // The item slot alternates between two words: a wave that runs ahead into
   // the next iteration writes the other word, and cannot come back to this
   // one before every wave has passed the next barrier (and so has read it).
+  const int home = static_cast<int>(blockIdx.x % kXcdQueues);
   for (int it = 0;; it ^= 1) {
-    if (threadIdx.x == 0) s_item[it] = atomicAdd(counter, 1u);
+    if (threadIdx.x == 0) {
+      uint32_t item = 0xFFFFFFFFu;  // none left
+      for (int d = 0; d < kXcdQueues; ++d) {
+        const int q = (home + d) % kXcdQueues;
+        const uint32_t b = queue_begin(n_items, q), e = queue_begin(n_items, q + 1);
+        if (b == e) continue;
+        const uint32_t i = atomicAdd(&counter[q], 1u);
+        if (i < e - b) {
+          item = b + i;
+          break;
+        }
+      }
+      s_item[it] = item;
+    }
     __syncthreads();
     // uniform values: view records and tile indices stay in scalar registers
     const uint32_t item = __builtin_amdgcn_readfirstlane(s_item[it]);
@@ -463,7 +486,9 @@ render_quantile_batched_grid_kernel(const qr_view* __restrict__ views,
                     nullptr, nullptr);
 }
 
-__global__ void reset_counter_kernel(uint32_t* __restrict__ c) { *c = 0u; }
+__global__ void reset_counter_kernel(uint32_t* __restrict__ c) {
+  if (threadIdx.x < kXcdQueues) c[threadIdx.x] = 0u;
+}
 
 }  // namespace qr
 
@@ -513,8 +538,9 @@ extern "C" int qr_render_quantile_batched(void* stream, int32_t n_views, const q
   if (!views || !schedule || !prm)
     return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: null pointer");
   if (n_workgroups < 0) return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: n_workgroups < 0");
-  if (n_workgroups > 0 && (!workspace || workspace_bytes < sizeof(uint32_t)))
-    return fail(QR_ERR_CAPACITY, "qr_render_quantile_batched: persistent mode needs a 4-byte workspace");
+  if (n_workgroups > 0 && (!workspace || workspace_bytes < kXcdQueues * sizeof(uint32_t)))
+    return fail(QR_ERR_CAPACITY, "qr_render_quantile_batched: persistent mode needs a %d-byte workspace",
+                static_cast<int>(kXcdQueues * sizeof(uint32_t)));
   if (n_items < 0 || n_items >= (1ll << 31))
     return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: bad item count");
   if (K < 1 || K > QR_MAX_K)
@@ -542,7 +568,7 @@ extern "C" int qr_render_quantile_batched(void* stream, int32_t n_views, const q
     return check_launch("qr_render_quantile_batched");
   }
   auto* counter = static_cast<uint32_t*>(workspace);
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
 #define QR_LAUNCH(DT)                                                                             \
   hipLaunchKernelGGL(render_quantile_batched_kernel<DT>, dim3(n_workgroups), dim3(kTilePix), lds, \
                      s, views, schedule, n_items, counter, *prm, K, dim)

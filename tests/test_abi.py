@@ -125,6 +125,7 @@ def test_batched_validation(L):
     assert b(1, 10, -1, None, 0) == L.QR_ERR_INVALID_ARG
     assert b(1, 10, 4, None, 0) == L.QR_ERR_CAPACITY  # persistent mode needs the counter
     assert b(1, 10, 4, d, 2) == L.QR_ERR_CAPACITY
+    assert b(1, 10, 4, d, 16) == L.QR_ERR_CAPACITY  # one 4-byte counter per XCD
     assert b(1, 1 << 31, 0, None, 0) == L.QR_ERR_INVALID_ARG
     assert b(1, 10, 0, None, 0, K=0) == L.QR_ERR_UNSUPPORTED
     assert b(1, 10, 0, None, 0, dtype=9) == L.QR_ERR_UNSUPPORTED
