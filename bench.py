@@ -187,9 +187,9 @@ def timed_batched(states, steps, warmup, schedule, wg_per_cu, overlap=True):
         for i in range(k):
             X, Y = states[i % 2], states[(i + 1) % 2]
             main.wait_event(X.front_done)
-            if evs is not None:
-                evs[i][0].record(main)
-            X.bq.render(schedule, wg_per_cu)
+            # the start event follows the schedule build: the events bracket
+            # the render launch itself
+            X.bq.render(schedule, wg_per_cu, start_event=evs[i][0] if evs is not None else None)
             if evs is not None:
                 evs[i][1].record(main)
             X.render_done.record(main)

@@ -60,10 +60,14 @@ class BatchedQuantile:
             return self.heavy
         raise ValueError(kind)
 
-    def render(self, kind: str = "natural", wg_per_cu: int = 0):
+    def render(self, kind: str = "natural", wg_per_cu: int = 0, start_event=None):
         """wg_per_cu 0: one workgroup per (view, tile) item; > 0: that many
-        persistent workgroups per CU taking items through a work counter."""
+        persistent workgroups per CU taking items through per-XCD work
+        counters. start_event (optional) is recorded on the current stream
+        after the schedule is built, right before the render launch."""
         sched = self.schedule(kind)
+        if start_event is not None:
+            start_event.record()
         L.qr_render_quantile_batched(self.n_views, self.views_dev, self.params, self.K,
                                      self.dtype_code, self.dim, sched, self.n_cu * wg_per_cu,
                                      self.counter if wg_per_cu > 0 else None)
