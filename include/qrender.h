@@ -110,6 +110,17 @@ typedef struct qr_view {
   int32_t width, height;
 } qr_view;
 
+/* Gradient buffers of one view of a batched backward
+ * (qr_render_quantile_batched_backward); device pointers with the meaning of
+ * the same-named qr_render_quantile_backward arguments. Views of one scene
+ * may share (and so accumulate into) the same gradient arrays. */
+typedef struct qr_view_grad {
+  const float* grad_out;
+  float* grad_features;
+  float* grad_means2d;
+  float* grad_conic_opacity;
+} qr_view_grad;
+
 /* Library version string (static storage). */
 const char* qr_version(void);
 
@@ -335,6 +346,26 @@ int qr_render_quantile_backward(void* stream, int32_t width, int32_t height,
                                 const float* feature_scale, int32_t dim,
                                 const float* grad_out, float* grad_features,
                                 float* grad_means2d, float* grad_conic_opacity);
+
+/*
+ * qr_render_quantile_batched_backward - qr_render_quantile_backward for many
+ * views in one launch over the (view, tile) items of `schedule`, the same
+ * schedule format and launch modes as qr_render_quantile_batched (n_workgroups
+ * = 0: one workgroup per item; > 0: persistent workgroups on per-XCD work
+ * queues held in `workspace`, device, >= 32 bytes). `views` (device
+ * qr_view[n_views]; out, T_q and n_sel are not used) and `grads` (device
+ * qr_view_grad[n_views]) describe view v of every item (v << QR_BATCH_TILE_BITS)
+ * | tile. Gradients are accumulated with atomic adds, so views of one scene
+ * may share gradient arrays (their sum is the scene's gradient); the order of
+ * the additions is unspecified.
+ * Errors: as qr_render_quantile_batched.
+ */
+int qr_render_quantile_batched_backward(void* stream, int32_t n_views, const qr_view* views,
+                                        const qr_view_grad* grads, const qr_params* prm,
+                                        int32_t K, int32_t dtype, int32_t dim,
+                                        const uint32_t* schedule, int64_t n_items,
+                                        int32_t n_workgroups, void* workspace,
+                                        size_t workspace_bytes);
 
 /*
  * qr_quantize_features - encodes a float32 feature table f32[N,dim] for

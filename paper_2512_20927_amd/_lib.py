@@ -29,6 +29,7 @@ EXPORTED = [
     "qr_bin_sort_workspace_size", "qr_bin_sort", "qr_render_dense", "qr_render_quantile",
     "qr_render_dense_backward", "qr_render_quantile_backward", "qr_quantize_features",
     "qr_render_quantile_batched", "qr_batch_schedule", "qr_project_views", "qr_bin_sort_views",
+    "qr_render_quantile_batched_backward",
 ]
 QR_BATCH_TILE_BITS = 20
 
@@ -53,6 +54,11 @@ class qr_view(ctypes.Structure):
                 ("features", ctypes.c_void_p), ("feature_scale", ctypes.c_void_p),
                 ("out", ctypes.c_void_p), ("T_q", ctypes.c_void_p), ("n_sel", ctypes.c_void_p),
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class qr_view_grad(ctypes.Structure):
+    _fields_ = [("grad_out", ctypes.c_void_p), ("grad_features", ctypes.c_void_p),
+                ("grad_means2d", ctypes.c_void_p), ("grad_conic_opacity", ctypes.c_void_p)]
 
 
 class qr_params(ctypes.Structure):
@@ -85,6 +91,7 @@ def _load():
         "qr_quantize_features": ([P, i64, i32, P, i32, P, P], i32),
         "qr_render_quantile_batched": ([P, i32, P, prm_p, i32, i32, i32, P, i64, i32, P, sz], i32),
         "qr_batch_schedule": ([P, i32, P, P, i64, P, P, sz], i32),
+        "qr_render_quantile_batched_backward": ([P, i32, P, P, prm_p, i32, i32, i32, P, i64, i32, P, sz], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -386,6 +393,35 @@ def qr_render_quantile_batched(n_views, views_dev, params, K, dtype_code, dim, s
                                            _ptr(schedule), schedule.numel(), n_workgroups,
                                            _ptr(workspace) if workspace is not None else None,
                                            ws_bytes))
+
+
+def qr_render_quantile_batched_backward(n_views, views_dev, grads_dev, params, K, dtype_code, dim,
+                                        schedule, n_workgroups, workspace, stream=None):
+    """Backward of qr_render_quantile_batched over the same views and
+    schedule; grads_dev: uint8 device tensor holding n_views qr_view_grad
+    records (see pack_grads)."""
+    if views_dev.numel() < n_views * ctypes.sizeof(qr_view):
+        raise ValueError("views_dev is smaller than n_views qr_view records")
+    if grads_dev.numel() < n_views * ctypes.sizeof(qr_view_grad):
+        raise ValueError("grads_dev is smaller than n_views qr_view_grad records")
+    _need(schedule, 0, I32, "schedule")
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(_LIB.qr_render_quantile_batched_backward(
+        _stream(stream), n_views, _ptr(views_dev), _ptr(grads_dev), ctypes.byref(params), K,
+        dtype_code, dim, _ptr(schedule), schedule.numel(), n_workgroups,
+        _ptr(workspace) if workspace is not None else None, ws_bytes))
+
+
+def pack_grads(grads) -> bytes:
+    """Host bytes of a qr_view_grad array; `grads` are dicts with grad_out
+    and (each optional) grad_features, grad_means2d, grad_conic_opacity."""
+    arr = (qr_view_grad * len(grads))()
+    for i, g in enumerate(grads):
+        arr[i].grad_out = g["grad_out"].data_ptr()
+        for f in ("grad_features", "grad_means2d", "grad_conic_opacity"):
+            t = g.get(f)
+            setattr(arr[i], f, t.data_ptr() if t is not None else None)
+    return bytes(arr)
 
 
 def pack_views(views) -> bytes:

@@ -10,7 +10,8 @@ schedules (item orders) are available: ``natural`` (view-major order, fixed)
 and ``heavy`` (longest tile lists first, built on the device by
 ``qr_batch_schedule`` from the current bins, so no host round trip). The
 autotuner times the candidates (schedule x workgroups per CU) with HIP events
-and caches the winner as JSON keyed by device, shapes and K.
+and caches the winner as JSON keyed by device, shapes and K. ``backward``
+runs the Q-Render backward of every view in one launch over the same items.
 """
 
 from __future__ import annotations
@@ -71,6 +72,34 @@ class BatchedQuantile:
         L.qr_render_quantile_batched(self.n_views, self.views_dev, self.params, self.K,
                                      self.dtype_code, self.dim, sched, self.n_cu * wg_per_cu,
                                      self.counter if wg_per_cu > 0 else None)
+
+    def set_grads(self, grads):
+        """grads: one dict per view (same order as the views) with grad_out
+        f32[H, W, dim] and the accumulated gradient tensors grad_features,
+        grad_means2d, grad_conic_opacity (each may be None; views of one scene
+        may share them). Validated against the views' shapes."""
+        if len(grads) != self.n_views:
+            raise ValueError("need one gradient record per view")
+        for v, g in zip(self._views, grads):
+            n, dim = v["features"].shape[0], self.dim
+            L._need(g["grad_out"], v["width"] * v["height"] * dim, L.F32, "grad_out")
+            for f, per in (("grad_features", dim), ("grad_means2d", 2), ("grad_conic_opacity", 4)):
+                if g.get(f) is not None:
+                    L._need(g[f], n * per, L.F32, f)
+        self._grads = grads  # keeps the tensors alive
+        raw = L.pack_grads(grads)
+        self.grads_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.views_dev.device)
+
+    def backward(self, kind: str = "natural", wg_per_cu: int = 0):
+        """Accumulates the Q-Render gradients of every view (set_grads) in
+        one launch; same launch shapes as render."""
+        if getattr(self, "grads_dev", None) is None:
+            raise RuntimeError("set_grads() first")
+        sched = self.schedule(kind)
+        L.qr_render_quantile_batched_backward(self.n_views, self.views_dev, self.grads_dev,
+                                              self.params, self.K, self.dtype_code, self.dim,
+                                              sched, self.n_cu * wg_per_cu,
+                                              self.counter if wg_per_cu > 0 else None)
 
     def key(self) -> str:
         shapes = sorted({(v["width"], v["height"]) for v in self._views})

@@ -26,6 +26,7 @@ SOURCES = [
     "render_quantile.hip",
     "render_dense.hip",
     "render_backward.hip",
+    "render_quantile_backward.hip",
     "quantize.hip",
     "schedule.hip",
 ]

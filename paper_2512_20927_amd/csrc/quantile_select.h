@@ -1,0 +1,250 @@
+// Selection phase of Quantile Rendering (Algorithm 1, Sec. 4.2) for one
+// 16x16 tile, shared by the forward renderer and its backward pass so that
+// both make exactly the same selections:
+//  - the walk: the tile's depth-sorted list is staged into LDS in batches of
+//    256 projected records and every pixel (one thread each) runs the
+//    transmittance chain T_test = T (1 - alpha') with the threshold test
+//    T_test < t_{k+1}, recording the <= K selected list positions and their
+//    weights w^Q = T^Q alpha'; a pixel is done once all K thresholds are
+//    consumed (the same event as the stop test T_test < 1/(K+1)) and the
+//    workgroup leaves the list once every pixel is done;
+//  - the merge: each group of four adjacent pixels (a row segment of the
+//    tile) has its four selection lists, ordered by list position, merged
+//    into its distinct selections, each carrying the four pixels' weights
+//    divided by the pixel's 1 - T^Q (0 where a pixel did not select it) and a
+//    mask of the pixels that selected it. The pixels of wave w are tile rows
+//    4w .. 4w+3, exactly the pixels of the groups it merges, so the merge and
+//    everything after it are wave-local.
+#pragma once
+
+#include "common.h"
+#include "render_common.h"
+
+namespace qr {
+
+constexpr int kViewShift = QR_BATCH_TILE_BITS;
+constexpr uint32_t kTileMask = (1u << QR_BATCH_TILE_BITS) - 1u;
+
+constexpr int kPG = 4;                     // pixels gathered together
+constexpr int kGroups = kTilePix / kPG;    // 64 pixel groups per tile
+#ifndef QR_UCAP
+#define QR_UCAP 16
+#endif
+constexpr int kUCap = QR_UCAP;             // distinct selections kept per group
+// Three 45 KB workgroups fill a CU's LDS: registers are bounded to match
+// (three waves per SIMD).
+constexpr int kWavesPerSimd = 3;
+
+// LDS of one workgroup: record staging, thresholds, per-pixel scalars and
+// the merged groups (each pixel's [K] selections live in dynamic LDS).
+struct QuantileLds {
+  float2 mean[kTilePix];
+  float4 co[kTilePix];
+  float thr[QR_MAX_K + 1];
+  float inv[kTilePix];
+  int ns[kTilePix];
+  int unum[kGroups];                       // distinct entries per group, -1 if over kUCap
+  int ugid[kGroups * kUCap];               // a group's distinct selections (list positions until converted)
+  float4 uw[kGroups * kUCap];              // their weights for the group's four pixels, x = first pixel
+  uint8_t umask[kGroups * kUCap];          // bit q: pixel q of the group selected the entry
+};
+
+struct ViewArgs {
+  int W, H;
+  const uint32_t* __restrict__ tile_offsets;
+  const uint32_t* __restrict__ sorted_gid;
+  const float2* __restrict__ means2d;
+  const float4* __restrict__ conic_opacity;
+  const void* __restrict__ feats;
+  const float* __restrict__ scale;
+  float* __restrict__ out;
+  float* __restrict__ T_q;
+  int32_t* __restrict__ n_sel;
+};
+
+// The same view with global-memory pointers (see QR_GLOBAL), as the tile
+// code uses it.
+struct GView {
+  int W, H;
+  const QR_GLOBAL uint32_t* __restrict__ tile_offsets;
+  const QR_GLOBAL uint32_t* __restrict__ sorted_gid;
+  const QR_GLOBAL f32x2* __restrict__ means2d;
+  const QR_GLOBAL f32x4* __restrict__ conic_opacity;
+  const QR_GLOBAL void* __restrict__ feats;
+  const QR_GLOBAL float* __restrict__ scale;
+  QR_GLOBAL float* __restrict__ out;
+  QR_GLOBAL float* __restrict__ T_q;
+  QR_GLOBAL int32_t* __restrict__ n_sel;
+};
+
+__device__ __forceinline__ GView to_global(const ViewArgs& v) {
+  return GView{v.W, v.H,
+               (const QR_GLOBAL uint32_t*)v.tile_offsets, (const QR_GLOBAL uint32_t*)v.sorted_gid,
+               (const QR_GLOBAL f32x2*)v.means2d, (const QR_GLOBAL f32x4*)v.conic_opacity,
+               (const QR_GLOBAL void*)v.feats, (const QR_GLOBAL float*)v.scale,
+               (QR_GLOBAL float*)v.out, (QR_GLOBAL float*)v.T_q, (QR_GLOBAL int32_t*)v.n_sel};
+}
+
+// Orders this wave's LDS writes before its later LDS reads (all lanes).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ ViewArgs view_args(const qr_view& qv) {
+  return ViewArgs{qv.width, qv.height, qv.tile_offsets, qv.sorted_gid,
+                  reinterpret_cast<const float2*>(qv.means2d),
+                  reinterpret_cast<const float4*>(qv.conic_opacity), qv.features,
+                  qv.feature_scale, qv.out, qv.T_q, qv.n_sel};
+}
+
+// What the walk leaves in registers for the calling thread's pixel.
+struct PixelSel {
+  int ns;    // selections (0 outside the image)
+  float TQ;  // T^Q after the last selection
+};
+
+// Runs the walk and the merge for one tile (all 256 threads of the
+// workgroup). Selections go to s_sel_pos / s_sel_w ([256][KP], as absolute
+// positions in sorted_gid and w^Q); L receives ns (-1 outside the image),
+// 1 / (1 - T^Q) and the merged groups with Gaussian ids; if upos is given it
+// receives the merged groups' list positions ([kGroups][kUCap]). Workgroup barriers
+// occur only around the staging of record batches; the record batch is only
+// rewritten after a barrier that every wave reaches once it has finished the
+// previous tile.
+__device__ __forceinline__ PixelSel quantile_select(const GView& v, int lo, int hi, int K,
+                                                    float pxc, float pyc, bool inside,
+                                                    const qr_params& prm, QuantileLds& L,
+                                                    int* __restrict__ s_sel_pos,
+                                                    float* __restrict__ s_sel_w, int KP,
+                                                    int* __restrict__ upos = nullptr) {
+  const int tid = threadIdx.x;
+  // thr[k] = t_{k+1}; thr[K] = 0 (identical for every tile of a launch)
+  if (tid <= K) L.thr[tid] = quantile_threshold(tid + 1, K);
+
+  float T = 1.f, TQ = 1.f;
+  int k = 0, ns = 0;
+  bool done = !inside;
+  float thr_k = quantile_threshold(1, K);  // t_{k+1}: changes only at a crossing
+  int* my_pos = s_sel_pos + tid * KP;
+  float* my_w = s_sel_w + tid * KP;
+  const float amin = prm.alpha_min, amax = prm.alpha_max;
+
+  for (int batch = lo; batch < hi; batch += kTilePix) {
+    if (__syncthreads_count(!done) == 0) break;
+    const int idx = batch + tid;
+    if (idx < hi) {
+      const int g = static_cast<int>(v.sorted_gid[idx]);
+      const f32x2 m = v.means2d[g];
+      const f32x4 c = v.conic_opacity[g];
+      L.mean[tid] = make_float2(m.x, m.y);
+      L.co[tid] = make_float4(c.x, c.y, c.z, c.w);
+    } else {  // padding record: opacity 0 is below alpha_min on every ray
+      L.mean[tid] = make_float2(0.f, 0.f);
+      L.co[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __syncthreads();
+    // kWalkUnroll records are read from LDS before any is used (one LDS round
+    // trip per group of records; the padding makes every group whole)
+    constexpr int kWalkUnroll = 8;
+    const int cnt_pad = (min(kTilePix, hi - batch) + kWalkUnroll - 1) & ~(kWalkUnroll - 1);
+    for (int j = 0; j < cnt_pad; j += kWalkUnroll) {
+      if (__all(done)) break;
+      float2 rm[kWalkUnroll];
+      float4 rc[kWalkUnroll];
+#pragma unroll
+      for (int u = 0; u < kWalkUnroll; ++u) {
+        rm[u] = L.mean[j + u];
+        rc[u] = L.co[j + u];
+      }
+#pragma unroll
+      for (int u = 0; u < kWalkUnroll; ++u) {
+        const float alpha = gauss_alpha(rm[u], rc[u], pxc, pyc, amax);
+        if (done || alpha < amin) continue;  // finished, or not on this pixel's ray
+        const float T_test = T * (1.f - alpha);
+        if (T_test < thr_k) {  // crossing: a quantile Gaussian
+          my_pos[ns] = batch + j + u;
+          my_w[ns] = TQ * alpha;
+          ++ns;
+          TQ = TQ * (1.f - alpha);
+          ++k;
+          while (k < K && T_test < L.thr[k]) ++k;  // thresholds crossed by the same step
+          thr_k = L.thr[k];
+          if (k == K) done = true;
+        }
+        T = T_test;
+      }
+    }
+  }
+  L.ns[tid] = inside ? ns : -1;
+  L.inv[tid] = ns > 0 ? 1.f / (1.f - TQ) : 0.f;
+  wave_lds_sync();
+
+  // The merge, wave-local: adjacent pixels select mostly the same
+  // Gaussians, so a group's distinct selections are far fewer than its
+  // pixels' selections. Lane l < 16 merges group 16 w + l.
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  constexpr int kWaveGroups = kGroups / 4;
+  if (lane < kWaveGroups) {
+    const int grp = wave * kWaveGroups + lane;
+    const int p0 = grp * kPG;
+    // each pixel's next selection (list position and weight) kept in registers
+    // (weights are stored already divided by the pixel's 1 - T^Q)
+    int n[kPG], idx[kPG], head[kPG];
+    float hw[kPG], inv[kPG];
+#pragma unroll
+    for (int q = 0; q < kPG; ++q) {
+      n[q] = max(L.ns[p0 + q], 0);
+      inv[q] = L.inv[p0 + q];
+      idx[q] = 0;
+      head[q] = n[q] > 0 ? s_sel_pos[(p0 + q) * KP] : 0x7fffffff;
+      hw[q] = n[q] > 0 ? s_sel_w[(p0 + q) * KP] * inv[q] : 0.f;
+    }
+    int cnt = 0;
+    for (;;) {
+      const int best = min(min(head[0], head[1]), min(head[2], head[3]));
+      if (best == 0x7fffffff) break;
+      if (cnt == kUCap) {
+        cnt = -1;
+        break;
+      }
+      float wq[kPG];
+      uint32_t mk = 0u;
+#pragma unroll
+      for (int q = 0; q < kPG; ++q) {
+        wq[q] = 0.f;
+        if (head[q] == best) {
+          wq[q] = hw[q];
+          mk |= 1u << q;
+          ++idx[q];
+          head[q] = idx[q] < n[q] ? s_sel_pos[(p0 + q) * KP + idx[q]] : 0x7fffffff;
+          hw[q] = idx[q] < n[q] ? s_sel_w[(p0 + q) * KP + idx[q]] * inv[q] : 0.f;
+        }
+      }
+      L.ugid[grp * kUCap + cnt] = best;  // position for now
+      L.uw[grp * kUCap + cnt] = make_float4(wq[0], wq[1], wq[2], wq[3]);
+      L.umask[grp * kUCap + cnt] = static_cast<uint8_t>(mk);
+      ++cnt;
+    }
+    L.unum[grp] = cnt;
+    // positions -> Gaussian ids: all loads issued before any result is used
+    int pos[kUCap];
+#pragma unroll
+    for (int e = 0; e < kUCap; ++e) pos[e] = e < cnt ? L.ugid[grp * kUCap + e] : -1;
+    uint32_t gid[kUCap];
+#pragma unroll
+    for (int e = 0; e < kUCap; ++e) gid[e] = pos[e] >= 0 ? v.sorted_gid[pos[e]] : 0u;
+#pragma unroll
+    for (int e = 0; e < kUCap; ++e) {
+      if (e < cnt) {
+        L.ugid[grp * kUCap + e] = static_cast<int>(gid[e]);
+        if (upos) upos[grp * kUCap + e] = pos[e];
+      }
+    }
+  }
+  wave_lds_sync();
+  return PixelSel{ns, TQ};
+}
+
+}  // namespace qr

@@ -1,18 +1,14 @@
-// Backward passes of Quantile Rendering (Algorithm 1) and of the dense blend
-// (Eq. 1): gradients with respect to the decoded float32 features, the 2D
-// means, the conics (a, b, c) and the opacities.
+// Backward pass of the dense blend (Eq. 1): gradients with respect to the
+// decoded float32 features, the 2D means, the conics (a, b, c) and the
+// opacities. (The Quantile Rendering backward is in
+// render_quantile_backward.hip.)
 //
-// Both kernels re-run the forward walk of their tile with the identical
-// float32 arithmetic (same helpers, same operation order), so exactly the
-// entries the forward blended or selected are differentiated, and take
-// transmittances from that recomputation instead of stored per-pixel lists.
+// The kernel re-runs the forward walk of its tile with the identical float32
+// arithmetic (same helpers, same operation order), so exactly the entries
+// the forward blended are differentiated, and takes transmittances from that
+// recomputation instead of stored per-pixel lists.
 //
-// With g = dL/d(out_p) and d_i = <g, f_i>:
-//  quantile (selected j, w_j = T^Q_j alpha'_j, Z = 1 - T^Q, out = sum w f / Z)
-//    dL/df_j      = (w_j / Z) g
-//    dL/dalpha'_j = (T^Q_j d_j - (S_j + <g, out> T^Q) / (1 - alpha'_j)) / Z,
-//                   S_j = sum_{l > j} w_l d_l
-//  dense (w_i = T_i alpha'_i, out = sum w f)
+// With g = dL/d(out_p), d_i = <g, f_i>, w_i = T_i alpha'_i, out = sum w f:
 //    dL/df_i      = w_i g
 //    dL/dalpha'_i = T_i d_i - (<g, out> - sum_{l <= i} w_l d_l) / (1 - alpha'_i)
 // and alpha' = o G, G = exp(-(a dx^2 + 2 b dx dy + c dy^2)/2) gives
@@ -30,24 +26,6 @@ namespace qr {
 
 constexpr int kCW = 32;          // feature columns staged per chunk
 constexpr int kGStride = kCW + 1;  // LDS row stride of the grad_out chunk
-constexpr int kWin = 256;        // list positions grouped per window
-
-__device__ __forceinline__ void chain_geometry(float dL_dalpha, const AlphaEval& e, float4 co,
-                                               int g, float* __restrict__ grad_means2d,
-                                               float* __restrict__ grad_co) {
-  if (e.clamped || dL_dalpha == 0.f) return;
-  const float dpow = dL_dalpha * e.alpha;
-  if (grad_co) {
-    atomicAdd(&grad_co[4 * g + 0], dpow * (-0.5f * e.dx * e.dx));
-    atomicAdd(&grad_co[4 * g + 1], dpow * (-e.dx * e.dy));
-    atomicAdd(&grad_co[4 * g + 2], dpow * (-0.5f * e.dy * e.dy));
-    atomicAdd(&grad_co[4 * g + 3], dL_dalpha * e.G);
-  }
-  if (grad_means2d) {
-    atomicAdd(&grad_means2d[2 * g + 0], dpow * (co.x * e.dx + co.y * e.dy));
-    atomicAdd(&grad_means2d[2 * g + 1], dpow * (co.y * e.dx + co.z * e.dy));
-  }
-}
 
 // Loads the [256 px x kCW] slice [c0, c0 + kCW) of the tile's grad_out into
 // LDS (rows of pixels outside the image are zero).
@@ -62,210 +40,6 @@ __device__ __forceinline__ void load_grad_chunk(float* s_g, const QR_GLOBAL floa
       v = *reinterpret_cast<const QR_GLOBAL f32x4*>(grad_out + (static_cast<int64_t>(gy) * W + gx) * dim + c0 + 4 * c4);
     float* r = s_g + p * kGStride + 4 * c4;
     r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
-  }
-}
-
-// ============================================================================
-// Quantile Rendering backward. One workgroup per tile, one thread per pixel.
-//  A. re-run Algorithm 1; keep each selection's list position, w^Q and the
-//     T^Q before it in LDS;
-//  B. group the tile's selections by list position (counting sort in LDS), so
-//     that each selected Gaussian's feature gradient sum_p (w_pj / Z_p) g_p
-//     is formed once per tile from a grad_out chunk staged in LDS, then
-//     added to global memory once per column;
-//  C. with d_pj = <g_p, f_j> accumulated over the same chunks, a reverse sweep
-//     over each pixel's selections gives dL/dalpha' and the chain rule.
-// LDS is partitioned by hand: the record staging of A and the grad_out chunk
-// of B never live at the same time and share space.
-template <int DT, int KM>
-__global__ void __launch_bounds__(kTilePix)
-quantile_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm, int K,
-                         const uint32_t* __restrict__ tile_offsets,
-                         const uint32_t* __restrict__ sorted_gid,
-                         const float2* __restrict__ means2d,
-                         const float4* __restrict__ conic_opacity, const void* __restrict__ feats,
-                         const float* __restrict__ scale, int dim,
-                         const float* __restrict__ grad_out, float* __restrict__ grad_features,
-                         float* __restrict__ grad_means2d, float* __restrict__ grad_co) {
-  extern __shared__ unsigned char lds[];
-  const QR_GLOBAL void* gfeats = (const QR_GLOBAL void*)feats;
-  const QR_GLOBAL float* gscale = (const QR_GLOBAL float*)scale;
-  const QR_GLOBAL float* ggrad = (const QR_GLOBAL float*)grad_out;
-  // persistent arrays
-  int* s_pos = reinterpret_cast<int*>(lds);                          // [256][KM]
-  float* s_w = reinterpret_cast<float*>(s_pos + kTilePix * KM);     // [256][KM]
-  float* s_tq = s_w + kTilePix * KM;                                 // [256][KM]
-  uint16_t* s_item = reinterpret_cast<uint16_t*>(s_tq + kTilePix * KM);  // [256*KM]
-  float* s_invZ = reinterpret_cast<float*>(s_item + kTilePix * KM);  // [256]
-  int* s_ns = reinterpret_cast<int*>(s_invZ + kTilePix);             // [256]
-  uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_ns + kTilePix);    // [kWin]
-  uint32_t* s_start = s_cnt + kWin;                                  // [kWin]
-  int* s_upos = reinterpret_cast<int*>(s_start + kWin);              // [kWin]
-  int* s_ugid = s_upos + kWin;                                       // [kWin]
-  uint32_t* s_misc = reinterpret_cast<uint32_t*>(s_ugid + kWin);     // [8]
-  float* s_thr = reinterpret_cast<float*>(s_misc + 8);               // [QR_MAX_K + 1]
-  // phase-scoped union, 16-byte aligned (offset fixed at compile time, so
-  // every access keeps the LDS address space)
-  constexpr size_t kPersistBytes = static_cast<size_t>(kTilePix) * KM * (4 + 4 + 4 + 2) +
-                                   kTilePix * 8 + kWin * 16 + 8 * 4 + (QR_MAX_K + 1) * 4;
-  unsigned char* u = lds + ((kPersistBytes + 15) & ~static_cast<size_t>(15));
-  float4* s_co = reinterpret_cast<float4*>(u);                       // A: [256]
-  float2* s_mean = reinterpret_cast<float2*>(s_co + kTilePix);       // A: [256]
-  int* s_bgid = reinterpret_cast<int*>(s_mean + kTilePix);           // A: [256]
-  float* s_g = reinterpret_cast<float*>(u);                          // B: [256][kGStride]
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int tile = xcd_remap(blockIdx.x, n_tiles);
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int px = tx * kTile + (tid % kTile);
-  const int py = ty * kTile + (tid / kTile);
-  const bool inside = px < W && py < H;
-  const float pxc = px + 0.5f, pyc = py + 0.5f;
-  if (tid <= K) s_thr[tid] = quantile_threshold(tid + 1, K);
-  if (tid == 0) s_misc[0] = 0;  // largest selected position + 1
-  const int lo = static_cast<int>(tile_offsets[tile]);
-  const int hi = static_cast<int>(tile_offsets[tile + 1]);
-
-  // ---- A: selection walk (identical to the forward) ----
-  float T = 1.f, TQ = 1.f;
-  int k = 0, ns = 0;
-  bool done = !inside;
-  int* my_pos = s_pos + tid * KM;
-  float* my_w = s_w + tid * KM;
-  float* my_tq = s_tq + tid * KM;
-  for (int batch = lo; batch < hi; batch += kTilePix) {
-    if (__syncthreads_count(!done) == 0) break;
-    const int idx = batch + tid;
-    if (idx < hi) {
-      const int g = static_cast<int>(sorted_gid[idx]);
-      s_bgid[tid] = g;
-      s_mean[tid] = means2d[g];
-      s_co[tid] = conic_opacity[g];
-    }
-    __syncthreads();
-    const int cnt = min(kTilePix, hi - batch);
-    for (int j = 0; j < cnt && !done; ++j) {
-      const float alpha = gauss_alpha(s_mean[j], s_co[j], pxc, pyc, prm.alpha_max);
-      if (alpha < prm.alpha_min) continue;
-      const float T_test = T * (1.f - alpha);
-      if (T_test < s_thr[k]) {
-        my_pos[ns] = batch - lo + j;
-        my_w[ns] = TQ * alpha;
-        my_tq[ns] = TQ;
-        ++ns;
-        TQ = TQ * (1.f - alpha);
-        ++k;
-        while (k < K && T_test < s_thr[k]) ++k;
-        if (k == K) done = true;
-      }
-      T = T_test;
-    }
-  }
-  s_ns[tid] = ns;
-  s_invZ[tid] = ns > 0 ? 1.f / (1.f - TQ) : 0.f;
-  if (ns > 0) atomicMax(&s_misc[0], static_cast<uint32_t>(my_pos[ns - 1] + 1));
-  __syncthreads();
-  const int pos_end = static_cast<int>(s_misc[0]);
-  const float invZ = s_invZ[tid];
-
-  float d[KM];
-#pragma unroll
-  for (int j = 0; j < KM; ++j) d[j] = 0.f;
-
-  // ---- B: per position window, grouped feature gradients (+ dots) ----
-  for (int w0 = 0; w0 < pos_end; w0 += kWin) {
-    s_cnt[tid] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < KM; ++j)
-      if (j < ns && my_pos[j] >= w0 && my_pos[j] < w0 + kWin) atomicAdd(&s_cnt[my_pos[j] - w0], 1u);
-    __syncthreads();
-    const uint32_t c = s_cnt[tid];
-    uint32_t n_items, n_uniq;
-    const uint32_t start = block_scan_exclusive(c, s_misc + 4, &n_items);
-    const uint32_t uidx = block_scan_exclusive(c > 0 ? 1u : 0u, s_misc + 4, &n_uniq);
-    s_start[tid] = start;
-    if (c > 0) {
-      s_upos[uidx] = tid;
-      s_ugid[uidx] = static_cast<int>(sorted_gid[lo + w0 + tid]);
-    }
-    s_cnt[tid] = 0;  // reused as fill cursor
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < KM; ++j) {
-      if (j < ns && my_pos[j] >= w0 && my_pos[j] < w0 + kWin) {
-        const int r = my_pos[j] - w0;
-        const uint32_t slot = s_start[r] + atomicAdd(&s_cnt[r], 1u);
-        s_item[slot] = static_cast<uint16_t>((tid << 5) | j);
-      }
-    }
-    __syncthreads();
-
-    for (int c0 = 0; c0 < dim; c0 += kCW) {
-      load_grad_chunk(s_g, ggrad, W, H, tx, ty, dim, c0);
-      __syncthreads();
-      if (w0 == 0) {
-        // dots d_pj over this chunk, for all of this pixel's selections
-        const float* gr = s_g + tid * kGStride;
-#pragma unroll
-        for (int j = 0; j < KM; ++j) {
-          if (j < ns) {
-            const int g = static_cast<int>(sorted_gid[lo + my_pos[j]]);
-            float acc = 0.f;
-#pragma unroll
-            for (int c4 = 0; c4 < kCW / 4; ++c4) {
-              if (c0 + 4 * c4 >= dim) break;
-              const float4 f = load_feat4_global<DT>(gfeats, gscale, g, dim, c0 + 4 * c4);
-              acc += gr[4 * c4] * f.x + gr[4 * c4 + 1] * f.y + gr[4 * c4 + 2] * f.z + gr[4 * c4 + 3] * f.w;
-            }
-            d[j] += acc;
-          }
-        }
-      }
-      if (grad_features) {
-        // wave per selected position: lanes 0..31 and 32..63 take alternate
-        // items of the same column, then combine
-        const int col = lane & 31, half = lane >> 5;
-        for (int uq = wave; uq < static_cast<int>(n_uniq); uq += 4) {
-          const int r = s_upos[uq];
-          const uint32_t b = s_start[r], e = b + s_cnt[r];
-          float acc = 0.f;
-          for (uint32_t it = b + half; it < e; it += 2) {
-            const uint32_t item = s_item[it];
-            const int p = item >> 5, j = item & 31;
-            acc += s_w[p * KM + j] * s_invZ[p] * s_g[p * kGStride + col];
-          }
-          acc += __shfl_xor(acc, 32, 64);
-          if (half == 0 && c0 + col < dim)
-            atomicAdd(&grad_features[static_cast<int64_t>(s_ugid[uq]) * dim + c0 + col], acc);
-        }
-      }
-      __syncthreads();
-    }
-  }
-  (void)n_tiles;
-
-  // ---- C: reverse sweep over this pixel's selections ----
-  if (ns == 0 || (!grad_means2d && !grad_co)) return;
-  float gf = 0.f;
-#pragma unroll
-  for (int j = 0; j < KM; ++j)
-    if (j < ns) gf += my_w[j] * d[j];
-  gf *= invZ;  // <g, out>
-  float S = 0.f;
-#pragma unroll
-  for (int j = KM - 1; j >= 0; --j) {
-    if (j < ns) {
-      const int g = static_cast<int>(sorted_gid[lo + my_pos[j]]);
-      const float2 mean = means2d[g];
-      const float4 co = conic_opacity[g];
-      const AlphaEval e = eval_alpha(mean, co, pxc, pyc, prm.alpha_max);
-      const float one_m = 1.f - e.alpha;
-      const float dL_da = invZ * (my_tq[j] * d[j] - (S + gf * TQ) / one_m);
-      chain_geometry(dL_da, e, co, g, grad_means2d, grad_co);
-      S += my_w[j] * d[j];
-    }
   }
 }
 
@@ -464,54 +238,6 @@ inline int validate_backward(const char* name, const float* grad_out) {
 }  // namespace qr
 
 using namespace qr;
-
-extern "C" int qr_render_quantile_backward(void* stream, int32_t width, int32_t height,
-                                           const qr_params* prm, int32_t K,
-                                           const uint32_t* tile_offsets, const uint32_t* sorted_gid,
-                                           const float* means2d, const float* conic_opacity,
-                                           const void* features, int32_t dtype,
-                                           const float* feature_scale, int32_t dim,
-                                           const float* grad_out, float* grad_features,
-                                           float* grad_means2d, float* grad_conic_opacity) {
-  int rc = validate_render("qr_render_quantile_backward", width, height, prm, tile_offsets,
-                           sorted_gid, means2d, conic_opacity, features, dtype, feature_scale, dim,
-                           grad_out);
-  if (rc != QR_OK) return rc;
-  if (K < 1 || K > QR_MAX_K)
-    return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile_backward: K = %d outside [1, %d]", K, QR_MAX_K);
-  const int tiles_x = static_cast<int>(ceil_div(width, kTile));
-  const int tiles_y = static_cast<int>(ceil_div(height, kTile));
-  const int n_tiles = tiles_x * tiles_y;
-  hipStream_t s = as_stream(stream);
-  const int KM = K <= 8 ? 8 : (K <= 16 ? 16 : 32);
-  // persistent arrays + union (max of record staging and the grad_out chunk)
-  const size_t persistent = static_cast<size_t>(kTilePix) * KM * (4 + 4 + 4 + 2) + kTilePix * 8 +
-                            kWin * 16 + 8 * 4 + (QR_MAX_K + 1) * 4 + 16;
-  const size_t uni = std::max<size_t>(kTilePix * (16 + 8 + 4), kTilePix * kGStride * 4);
-  const size_t lds = persistent + uni;
-#define QR_LAUNCH(DT, KMV)                                                                         \
-  hipLaunchKernelGGL((quantile_backward_kernel<DT, KMV>), dim3(n_tiles), dim3(kTilePix), lds, s,   \
-                     width, height, tiles_x, n_tiles, *prm, K, tile_offsets, sorted_gid,           \
-                     reinterpret_cast<const float2*>(means2d),                                     \
-                     reinterpret_cast<const float4*>(conic_opacity), features, feature_scale, dim,  \
-                     grad_out, grad_features, grad_means2d, grad_conic_opacity)
-#define QR_DT(KMV)                                    \
-  switch (dtype) {                                    \
-    case QR_F32: QR_LAUNCH(QR_F32, KMV); break;       \
-    case QR_BF16: QR_LAUNCH(QR_BF16, KMV); break;     \
-    default: QR_LAUNCH(QR_FP8_E4M3, KMV); break;      \
-  }
-  if (KM == 8) {
-    QR_DT(8)
-  } else if (KM == 16) {
-    QR_DT(16)
-  } else {
-    QR_DT(32)
-  }
-#undef QR_DT
-#undef QR_LAUNCH
-  return check_launch("qr_render_quantile_backward");
-}
 
 extern "C" int qr_render_dense_backward(void* stream, int32_t width, int32_t height,
                                         const qr_params* prm, const uint32_t* tile_offsets,

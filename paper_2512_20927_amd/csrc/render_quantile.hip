@@ -1,7 +1,7 @@
 // Quantile Rendering forward (Algorithm 1, Sec. 4.2).
 //
 // One workgroup per 16x16 tile, one thread per pixel (4 wave64s).
-// Phase 1 (selection): the tile's depth-sorted list is staged into LDS in
+// Phase 1 (selection, quantile_select.h, shared with the backward): the tile's depth-sorted list is staged into LDS in
 // batches of 256 projected records; every pixel walks it front to back with
 // the transmittance chain T_test = T (1 - alpha') and the threshold test
 // T_test < t_{k+1}, recording the <= K selected (Gaussian id, w^Q) pairs in
@@ -18,79 +18,9 @@
 // stores. The map write is the dominant HBM traffic of the whole pipeline.
 // Everything after the walk is wave-local: wave w's pixels (tile rows
 // 4w .. 4w+3) are exactly the pixels of the groups it gathers.
-#include "common.h"
-#include "render_common.h"
+#include "quantile_select.h"
 
 namespace qr {
-
-constexpr int kViewShift = QR_BATCH_TILE_BITS;
-constexpr uint32_t kTileMask = (1u << QR_BATCH_TILE_BITS) - 1u;
-
-// LDS of one workgroup: record staging, thresholds, and each pixel's
-// selections (the [256][K] arrays live in dynamic LDS).
-constexpr int kPG = 4;                     // pixels gathered together
-constexpr int kGroups = kTilePix / kPG;    // 64 pixel groups per tile
-#ifndef QR_UCAP
-#define QR_UCAP 16
-#endif
-constexpr int kUCap = QR_UCAP;             // distinct selections kept per group
-// Three 45 KB workgroups fill a CU's LDS: registers are bounded to match
-// (three waves per SIMD).
-constexpr int kWavesPerSimd = 3;
-
-struct QuantileLds {
-  float2 mean[kTilePix];
-  float4 co[kTilePix];
-  float thr[QR_MAX_K + 1];
-  float inv[kTilePix];
-  int ns[kTilePix];
-  int unum[kGroups];                       // distinct entries per group, -1 if over kUCap
-  int ugid[kGroups * kUCap];               // a group's distinct selections (list positions until converted)
-  float4 uw[kGroups * kUCap];              // their weights for the group's four pixels, x = first pixel
-  uint8_t umask[kGroups * kUCap];          // bit q: pixel q of the group selected the entry
-};
-
-struct ViewArgs {
-  int W, H;
-  const uint32_t* __restrict__ tile_offsets;
-  const uint32_t* __restrict__ sorted_gid;
-  const float2* __restrict__ means2d;
-  const float4* __restrict__ conic_opacity;
-  const void* __restrict__ feats;
-  const float* __restrict__ scale;
-  float* __restrict__ out;
-  float* __restrict__ T_q;
-  int32_t* __restrict__ n_sel;
-};
-
-// The same view with global-memory pointers (see QR_GLOBAL), as the tile
-// code uses it.
-struct GView {
-  int W, H;
-  const QR_GLOBAL uint32_t* __restrict__ tile_offsets;
-  const QR_GLOBAL uint32_t* __restrict__ sorted_gid;
-  const QR_GLOBAL f32x2* __restrict__ means2d;
-  const QR_GLOBAL f32x4* __restrict__ conic_opacity;
-  const QR_GLOBAL void* __restrict__ feats;
-  const QR_GLOBAL float* __restrict__ scale;
-  QR_GLOBAL float* __restrict__ out;
-  QR_GLOBAL float* __restrict__ T_q;
-  QR_GLOBAL int32_t* __restrict__ n_sel;
-};
-
-__device__ __forceinline__ GView to_global(const ViewArgs& v) {
-  return GView{v.W, v.H,
-               (const QR_GLOBAL uint32_t*)v.tile_offsets, (const QR_GLOBAL uint32_t*)v.sorted_gid,
-               (const QR_GLOBAL f32x2*)v.means2d, (const QR_GLOBAL f32x4*)v.conic_opacity,
-               (const QR_GLOBAL void*)v.feats, (const QR_GLOBAL float*)v.scale,
-               (QR_GLOBAL float*)v.out, (QR_GLOBAL float*)v.T_q, (QR_GLOBAL int32_t*)v.n_sel};
-}
-
-// Orders this wave's LDS writes before its later LDS reads (all lanes).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
 
 // R distinct rows of a merged group, both column slots of the lane: all 2R
 // loads are requested before the first is used, then accumulated in row order.
@@ -244,134 +174,18 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
   const bool inside = px < W && py < H;
   const float pxc = px + 0.5f, pyc = py + 0.5f;
 
-  // thr[k] = t_{k+1}; thr[K] = 0 (identical for every tile of a launch)
-  if (tid <= K) L.thr[tid] = quantile_threshold(tid + 1, K);
-
   const int lo = static_cast<int>(v.tile_offsets[tile]);
   const int hi = static_cast<int>(v.tile_offsets[tile + 1]);
-
-  float T = 1.f, TQ = 1.f;
-  int k = 0, ns = 0;
-  bool done = !inside;
-  float thr_k = quantile_threshold(1, K);  // t_{k+1}: changes only at a crossing
   const int KP = (K + 3) & ~3;  // selection row stride: 16-byte aligned rows
-  int* s_sel_pos = s_sel_gid;  // selections are kept as tile-list positions
-  int* my_pos = s_sel_pos + tid * KP;
-  float* my_w = s_sel_w + tid * KP;
-  const float amin = prm.alpha_min, amax = prm.alpha_max;
-
-  for (int batch = lo; batch < hi; batch += kTilePix) {
-    if (__syncthreads_count(!done) == 0) break;
-    const int idx = batch + tid;
-    if (idx < hi) {
-      const int g = static_cast<int>(v.sorted_gid[idx]);
-      const f32x2 m = v.means2d[g];
-      const f32x4 c = v.conic_opacity[g];
-      L.mean[tid] = make_float2(m.x, m.y);
-      L.co[tid] = make_float4(c.x, c.y, c.z, c.w);
-    } else {  // padding record: opacity 0 is below alpha_min on every ray
-      L.mean[tid] = make_float2(0.f, 0.f);
-      L.co[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-    __syncthreads();
-    // kWalkUnroll records are read from LDS before any is used (one LDS round
-    // trip per group of records; the padding makes every group whole)
-    constexpr int kWalkUnroll = 8;
-    const int cnt_pad = (min(kTilePix, hi - batch) + kWalkUnroll - 1) & ~(kWalkUnroll - 1);
-    for (int j = 0; j < cnt_pad; j += kWalkUnroll) {
-      if (__all(done)) break;
-      float2 rm[kWalkUnroll];
-      float4 rc[kWalkUnroll];
-#pragma unroll
-      for (int u = 0; u < kWalkUnroll; ++u) {
-        rm[u] = L.mean[j + u];
-        rc[u] = L.co[j + u];
-      }
-#pragma unroll
-      for (int u = 0; u < kWalkUnroll; ++u) {
-        const float alpha = gauss_alpha(rm[u], rc[u], pxc, pyc, amax);
-        if (done || alpha < amin) continue;  // finished, or not on this pixel's ray
-        const float T_test = T * (1.f - alpha);
-        if (T_test < thr_k) {  // crossing: a quantile Gaussian
-          my_pos[ns] = batch + j + u;
-          my_w[ns] = TQ * alpha;
-          ++ns;
-          TQ = TQ * (1.f - alpha);
-          ++k;
-          while (k < K && T_test < L.thr[k]) ++k;  // thresholds crossed by the same step
-          thr_k = L.thr[k];
-          if (k == K) done = true;
-        }
-        T = T_test;
-      }
-    }
-  }
-  L.ns[tid] = inside ? ns : -1;
-  L.inv[tid] = ns > 0 ? 1.f / (1.f - TQ) : 0.f;
-  wave_lds_sync();
-
-  // Phase 2, wave-local: adjacent pixels select mostly the same Gaussians,
-  // so each group's four selection lists (ordered by list position) are
-  // merged into its distinct selections, each carrying the four pixels'
-  // weights (0 where a pixel did not select it), and every distinct row is
-  // loaded once per group. Lane l < 16 merges group 16 w + l.
+  int* s_sel_pos = s_sel_gid;   // selections are kept as tile-list positions
+  const PixelSel sel = quantile_select(v, lo, hi, K, pxc, pyc, inside, prm, L, s_sel_pos, s_sel_w, KP);
+  const int ns = sel.ns;
+  const float TQ = sel.TQ;
+  const int* my_pos = s_sel_pos + tid * KP;
+  const float* my_w = s_sel_w + tid * KP;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   constexpr int kWaveGroups = kGroups / 4;
-  if (lane < kWaveGroups) {
-    const int grp = wave * kWaveGroups + lane;
-    const int p0 = grp * kPG;
-    // each pixel's next selection (list position and weight) kept in registers
-    // (weights are stored already divided by the pixel's 1 - T^Q)
-    int n[kPG], idx[kPG], head[kPG];
-    float hw[kPG], inv[kPG];
-#pragma unroll
-    for (int q = 0; q < kPG; ++q) {
-      n[q] = max(L.ns[p0 + q], 0);
-      inv[q] = L.inv[p0 + q];
-      idx[q] = 0;
-      head[q] = n[q] > 0 ? s_sel_pos[(p0 + q) * KP] : 0x7fffffff;
-      hw[q] = n[q] > 0 ? s_sel_w[(p0 + q) * KP] * inv[q] : 0.f;
-    }
-    int cnt = 0;
-    for (;;) {
-      const int best = min(min(head[0], head[1]), min(head[2], head[3]));
-      if (best == 0x7fffffff) break;
-      if (cnt == kUCap) {
-        cnt = -1;
-        break;
-      }
-      float wq[kPG];
-      uint32_t mk = 0u;
-#pragma unroll
-      for (int q = 0; q < kPG; ++q) {
-        wq[q] = 0.f;
-        if (head[q] == best) {
-          wq[q] = hw[q];
-          mk |= 1u << q;
-          ++idx[q];
-          head[q] = idx[q] < n[q] ? s_sel_pos[(p0 + q) * KP + idx[q]] : 0x7fffffff;
-          hw[q] = idx[q] < n[q] ? s_sel_w[(p0 + q) * KP + idx[q]] * inv[q] : 0.f;
-        }
-      }
-      L.ugid[grp * kUCap + cnt] = best;  // position for now
-      L.uw[grp * kUCap + cnt] = make_float4(wq[0], wq[1], wq[2], wq[3]);
-      L.umask[grp * kUCap + cnt] = static_cast<uint8_t>(mk);
-      ++cnt;
-    }
-    L.unum[grp] = cnt;
-    // positions -> Gaussian ids: all loads issued before any result is used
-    int pos[kUCap];
-#pragma unroll
-    for (int e = 0; e < kUCap; ++e) pos[e] = e < cnt ? L.ugid[grp * kUCap + e] : -1;
-    uint32_t gid[kUCap];
-#pragma unroll
-    for (int e = 0; e < kUCap; ++e) gid[e] = pos[e] >= 0 ? v.sorted_gid[pos[e]] : 0u;
-#pragma unroll
-    for (int e = 0; e < kUCap; ++e)
-      if (e < cnt) L.ugid[grp * kUCap + e] = static_cast<int>(gid[e]);
-  }
-  wave_lds_sync();
   for (int gl = 0; gl < kWaveGroups; ++gl) {
     const int grp = wave * kWaveGroups + gl;
     const int nu = __builtin_amdgcn_readfirstlane(L.unum[grp]);
@@ -406,13 +220,6 @@ render_quantile_kernel(ViewArgs v, int n_tiles, qr_params prm, int K, int dim,
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);  // [256][KP]
   quantile_tile<DT>(to_global(v), xcd_remap(blockIdx.x, n_tiles), K, dim, prm, L, s_sel_gid,
                     s_sel_w, sel_gid_out, sel_w_out);
-}
-
-__device__ __forceinline__ ViewArgs view_args(const qr_view& qv) {
-  return ViewArgs{qv.width, qv.height, qv.tile_offsets, qv.sorted_gid,
-                  reinterpret_cast<const float2*>(qv.means2d),
-                  reinterpret_cast<const float4*>(qv.conic_opacity), qv.features,
-                  qv.feature_scale, qv.out, qv.T_q, qv.n_sel};
 }
 
 // Many views in one persistent launch. The schedule is cut into one

@@ -131,6 +131,19 @@ def test_batched_validation(L):
     assert b(1, 10, 0, None, 0, dtype=9) == L.QR_ERR_UNSUPPORTED
     assert b(1, 10, 0, None, 0, dim=24) == L.QR_ERR_UNSUPPORTED
     assert b(1, 0, 0, None, 0) == L.QR_OK  # nothing to render: no launch
+    def bb(n_views, n_items, n_wg, ws, ws_bytes, K=8, dtype=0, dim=16, grads=d):
+        return lib.qr_render_quantile_batched_backward(None, n_views, d, grads, P, K, dtype, dim, d,
+                                                       n_items, n_wg, ws, ws_bytes)
+
+    assert bb(0, 10, 0, None, 0) == L.QR_ERR_INVALID_ARG
+    assert bb(1, 10, 0, None, 0, grads=None) == L.QR_ERR_INVALID_ARG
+    assert bb(1, 10, -1, None, 0) == L.QR_ERR_INVALID_ARG
+    assert bb(1, 10, 4, d, 16) == L.QR_ERR_CAPACITY
+    assert bb(1, 1 << 31, 0, None, 0) == L.QR_ERR_INVALID_ARG
+    assert bb(1, 10, 0, None, 0, K=33) == L.QR_ERR_UNSUPPORTED
+    assert bb(1, 10, 0, None, 0, dtype=9) == L.QR_ERR_UNSUPPORTED
+    assert bb(1, 10, 0, None, 0, dim=24) == L.QR_ERR_UNSUPPORTED
+    assert bb(1, 0, 0, None, 0) == L.QR_OK
     rc = lib.qr_batch_schedule(None, 0, d, d, 10, d, d, 256)
     assert rc == L.QR_ERR_INVALID_ARG
     rc = lib.qr_batch_schedule(None, 2, d, d, 10, d, d, 16)
