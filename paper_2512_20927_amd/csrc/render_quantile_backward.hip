@@ -73,19 +73,24 @@ __device__ __forceinline__ float dpp(float v) {
                                                                0xF, 0xF, false));
 }
 
+__device__ __forceinline__ uint32_t fbits(float x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ float bitsf(uint32_t x) { return __builtin_bit_cast(float, x); }
+
 // Sums four per-lane partials (one per pixel of a group) over the 64 lanes
-// at once: halves of the wave exchange what the other half keeps, twice, so
-// that each 16-lane row is left with one pixel's partial sums, which DPP
-// moves add up inside the row. On return lanes 16q .. 16q+15 hold the total
-// of partial q.
-__device__ __forceinline__ float wave_sum4(float p0, float p1, float p2, float p3, int lane) {
-  const bool upper = lane >= 32;
-  float k0 = upper ? p2 : p0, k1 = upper ? p3 : p1;
-  k0 += __shfl_xor(upper ? p0 : p2, 32, 64);
-  k1 += __shfl_xor(upper ? p1 : p3, 32, 64);
-  const bool odd = (lane & 16) != 0;
-  float k = odd ? k1 : k0;
-  k += __shfl_xor(odd ? k0 : k1, 16, 64);
+// at once, without LDS: v_permlane32_swap exchanges lanes 32..63 of its first
+// operand with lanes 0..31 of its second, so after the swap of (p0, p2) the
+// sum of the two results holds p0 summed over the two halves in lanes 0..31
+// and p2 likewise in lanes 32..63 (the same for p1, p3); v_permlane16_swap
+// does the same with odd and even 16-lane rows, leaving row q with pixel q's
+// partial sums, which DPP moves add up inside the row. On return lanes
+// 16q .. 16q+15 hold the total of partial q.
+__device__ __forceinline__ float wave_sum4(float p0, float p1, float p2, float p3) {
+  const auto a = __builtin_amdgcn_permlane32_swap(fbits(p0), fbits(p2), false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(fbits(p1), fbits(p3), false, false);
+  const float x = bitsf(a[0]) + bitsf(a[1]);
+  const float y = bitsf(b[0]) + bitsf(b[1]);
+  const auto c = __builtin_amdgcn_permlane16_swap(fbits(x), fbits(y), false, false);
+  float k = bitsf(c[0]) + bitsf(c[1]);
   k += dpp<0xB1>(k);   // quad_perm [1,0,3,2]
   k += dpp<0x4E>(k);   // quad_perm [2,3,0,1]
   k += dpp<0x124>(k);  // row_ror:4
@@ -109,18 +114,20 @@ __device__ __forceinline__ float4 nt_load4(const QR_GLOBAL float* p) {
 // has LDS accumulators, flushed with one atomic per value at the end.
 // Selections past the slot capacity (or past kPosCap in the list) add to
 // global memory directly.
-constexpr int kSlotCap = 32;    // distinct selections of a tile with LDS sums
+constexpr int kAccRegs = 32;    // register sums per lane and column slot
+constexpr int kSlotCap = kAccRegs - 1;  // distinct selections of a tile with slots
 constexpr int kPosCap = 2048;   // list positions covered by the slot bitmap
 constexpr int kChunk = 128;     // feature columns summed per pass
 constexpr int kGeo = 6;         // d/d(a, b, c, o, u, v)
 
 struct BwdLds {
   int upos[kGroups * kUCap];        // merged rows' list positions
-  int8_t uslot[kGroups * kUCap];    // their slots, -1 if none
+  int8_t uslot[kGroups * kUCap];    // their slots, kSlotCap if none
+  uint32_t udefer[kGroups];         // per group: rows without a slot (bit e)
   uint32_t bm[kPosCap / 32];        // selected positions, relative to the list start
   int bpre[kPosCap / 32];           // slots before each bitmap word
   int sgid[kSlotCap];               // Gaussian id of each slot
-  float geo[kSlotCap * kGeo];       // geometric gradient sums
+  float geo[4][kSlotCap * kGeo];    // geometric gradient sums, per wave
   float acc[kSlotCap * kChunk];     // feature gradient sums of one column chunk
   int nslot;
 };
@@ -143,14 +150,14 @@ __device__ __forceinline__ void load_grad_row(const GView& v, const GGrad& gg, i
 }
 
 // Dots of R distinct rows of a merged group for one pass of 512 columns,
-// summed over the wave and added to s_d at the row's place in each
-// selecting pixel's list (byte q of sel counts the rows pixel q selected so
-// far).
+// summed over the wave and stored (first pass) or added to s_d at the row's
+// place in each selecting pixel's list (byte q of sel counts the rows pixel
+// q selected so far).
 template <int DT, int R>
 __device__ __forceinline__ void dot_rows(const GView& v, const int* ug, const uint8_t* um, int e0,
                                          int l0, int l1, int dim, const float4 (&g0)[kPG],
                                          const float4 (&g1)[kPG], float* __restrict__ s_d, int p0,
-                                         int KP, uint32_t& sel, int lane) {
+                                         int KP, uint32_t& sel, int lane, bool first) {
   float4 f0[R], f1[R];
 #pragma unroll
   for (int e = 0; e < R; ++e) {
@@ -165,10 +172,13 @@ __device__ __forceinline__ void dot_rows(const GView& v, const int* ug, const ui
 #pragma unroll
     for (int q = 0; q < kPG; ++q)
       if (mk & (1u << q)) pd[q] = dot8(g0[q], g1[q], f0[e], f1[e]);
-    const float t = wave_sum4(pd[0], pd[1], pd[2], pd[3], lane);
+    const float t = wave_sum4(pd[0], pd[1], pd[2], pd[3]);
     const int q = lane >> 4;
     const int j = static_cast<int>((sel >> (8 * q)) & 0xFFu);
-    if ((lane & 15) == 0 && (mk & (1u << q))) s_d[(p0 + q) * KP + j] += t;
+    if ((lane & 15) == 0 && (mk & (1u << q))) {
+      float* d = &s_d[(p0 + q) * KP + j];
+      *d = first ? t : *d + t;
+    }
     sel += (mk & 1u) | ((mk & 2u) << 7) | ((mk & 4u) << 14) | ((mk & 8u) << 21);
   }
 }
@@ -201,8 +211,12 @@ __device__ __forceinline__ void group_dots(const GView& v, const GGrad& gg, cons
       const uint8_t* um = &L.umask[grp * kUCap];
       uint32_t sel = 0u;
       int e0 = 0;
-      for (; e0 + 2 <= nu; e0 += 2) dot_rows<DT, 2>(v, ug, um, e0, l0, l1, dim, g0, g1, s_d, p0, KP, sel, lane);
-      if (e0 < nu) dot_rows<DT, 1>(v, ug, um, e0, l0, l1, dim, g0, g1, s_d, p0, KP, sel, lane);
+      for (; e0 + 4 <= nu; e0 += 4) dot_rows<DT, 4>(v, ug, um, e0, l0, l1, dim, g0, g1, s_d, p0, KP, sel, lane, cb == 0);
+      if (e0 + 2 <= nu) {
+        dot_rows<DT, 2>(v, ug, um, e0, l0, l1, dim, g0, g1, s_d, p0, KP, sel, lane, cb == 0);
+        e0 += 2;
+      }
+      if (e0 < nu) dot_rows<DT, 1>(v, ug, um, e0, l0, l1, dim, g0, g1, s_d, p0, KP, sel, lane, cb == 0);
     } else {  // more distinct selections than kUCap: pixel by pixel
 #pragma unroll
       for (int q = 0; q < kPG; ++q) {
@@ -213,21 +227,24 @@ __device__ __forceinline__ void group_dots(const GView& v, const GGrad& gg, cons
           const int g = static_cast<int>(__builtin_amdgcn_readfirstlane(v.sorted_gid[pos]));
           const float4 f0 = load_feat4_global<DT>(v.feats, v.scale, g, dim, 4 * l0);
           const float4 f1 = load_feat4_global<DT>(v.feats, v.scale, g, dim, 4 * l1);
-          const float t = wave_sum4(dot8(g0[q], g1[q], f0, f1), 0.f, 0.f, 0.f, lane);
-          if (lane == 0) s_d[p * KP + j] += t;
+          const float t = wave_sum4(dot8(g0[q], g1[q], f0, f1), 0.f, 0.f, 0.f);
+          if (lane == 0) s_d[p * KP + j] = cb == 0 ? t : s_d[p * KP + j] + t;
         }
       }
     }
   }
 }
 
-// Adds the feature gradient a (columns col and col + 64 of the chunk) of a
-// selection with slot s (or Gaussian g if s < 0).
-__device__ __forceinline__ void add_feature_grad(BwdLds& B, const GGrad& gg, int s, int g, int lane,
-                                                 int cb, int dim, float a0, float a1) {
+// Adds the feature gradient (a0, a1) (columns cb + lane and cb + 64 + lane)
+// of a selection to its slot's register sums (slot s, uniform: an indexed
+// register move), or to global memory for a selection without a slot
+// (Gaussian g).
+__device__ __forceinline__ void add_feature_grad(const GGrad& gg, int s, int g, int lane, int cb,
+                                                 int dim, float a0, float a1,
+                                                 float (&acc0)[kAccRegs], float (&acc1)[kAccRegs]) {
   if (s >= 0) {
-    atomicAdd(&B.acc[s * kChunk + lane], a0);
-    atomicAdd(&B.acc[s * kChunk + 64 + lane], a1);
+    acc0[s] += a0;
+    acc1[s] += a1;
   } else {
     QR_GLOBAL float* dst = gg.grad_features + static_cast<int64_t>(g) * dim + cb;
     if (cb + lane < dim) atomic_add(dst + lane, a0);
@@ -235,47 +252,97 @@ __device__ __forceinline__ void add_feature_grad(BwdLds& B, const GGrad& gg, int
   }
 }
 
-// Feature gradients of one group for the chunk of columns [cb, cb + 128):
-// sum_p (w_pj / Z_p) g_p per distinct row, into the slot sums.
-__device__ __forceinline__ void group_feature_grads(const GView& v, const GGrad& gg,
-                                                    const QuantileLds& L, BwdLds& B,
-                                                    const int* __restrict__ s_sel_pos,
-                                                    const float* __restrict__ s_sel_w, int KP,
-                                                    int grp, int nu, int lo, int tx, int ty,
-                                                    int lane, int cb, int dim) {
-  const int p0 = grp * kPG;
-  float g0[kPG], g1[kPG];
+// Columns cb + lane and cb + 64 + lane of the rows of dL/d(out) of batch h
+// (kBatch groups) of this wave's groups (the pixels of wave w are tile
+// pixels 64 w + lane). Exactly kGradBatchLoads(kBatch) loads are issued, none
+// skipped: addresses are clamped into the image and the columns into dim
+// (values of pixels outside the image, or with no selection, are never used:
+// no merged row carries their mask bit; columns past dim are never
+// written), so that a wait for all but the newest batch is a fixed count.
+template <int kBatch>
+constexpr int kGradBatchLoads = 2 * kBatch * kPG;
+
+template <int kBatch>
+__device__ __forceinline__ void load_grad_batch(const GView& v, const GGrad& gg, int wave,
+                                                int lane, int tx, int ty, int cb, int dim, int h,
+                                                float (&g0)[kBatch][kPG], float (&g1)[kBatch][kPG]) {
+  const int c0 = min(cb + lane, dim - 1), c1 = min(cb + 64 + lane, dim - 1);
 #pragma unroll
-  for (int q = 0; q < kPG; ++q) {
-    g0[q] = 0.f;
-    g1[q] = 0.f;
-    if (__builtin_amdgcn_readfirstlane(L.ns[p0 + q]) > 0) {
-      const int p = p0 + q;
-      const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
-      const QR_GLOBAL float* row = gg.grad_out + (static_cast<int64_t>(gy) * v.W + gx) * dim + cb;
-      if (cb + lane < dim) g0[q] = __builtin_nontemporal_load(row + lane);
-      if (cb + 64 + lane < dim) g1[q] = __builtin_nontemporal_load(row + 64 + lane);
+  for (int gi = 0; gi < kBatch; ++gi) {
+#pragma unroll
+    for (int q = 0; q < kPG; ++q) {
+      const int p = wave * 64 + (h * kBatch + gi) * kPG + q;
+      const int gx = min(tx * kTile + (p % kTile), v.W - 1);
+      const int gy = min(ty * kTile + (p / kTile), v.H - 1);
+      const QR_GLOBAL float* row = gg.grad_out + (static_cast<int64_t>(gy) * v.W + gx) * dim;
+      g0[gi][q] = __builtin_nontemporal_load(row + c0);
+      g1[gi][q] = __builtin_nontemporal_load(row + c1);
     }
   }
+}
+
+// s_waitcnt vmcnt(n) (gfx9 encoding: vmcnt in bits 3:0 and 15:14; expcnt
+// and lgkmcnt left at their maxima, i.e. not waited for).
+template <int n>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(n >= 0 && n < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
+}
+
+// Feature gradients of one group for the chunk of columns [cb, cb + 128):
+// sum_p (w_pj / Z_p) g_p per distinct row, into the wave's slot sums. g0 /
+// g1: the group's four rows of dL/d(out) at columns cb + lane and
+// cb + 64 + lane.
+__device__ __forceinline__ void group_feature_grads(const GView& v, const GGrad& gg,
+                                                    const QuantileLds& L, const BwdLds& B,
+                                                    const int* __restrict__ s_sel_pos,
+                                                    const float* __restrict__ s_sel_w, int KP,
+                                                    int grp, int lo, int lane, int cb, int dim,
+                                                    const float (&g0)[kPG], const float (&g1)[kPG],
+                                                    float (&acc0)[kAccRegs], float (&acc1)[kAccRegs]) {
+  const int p0 = grp * kPG;
+  const int nu = __builtin_amdgcn_readfirstlane(L.unum[grp]);
   if (nu >= 0) {
     const int* ug = &L.ugid[grp * kUCap];
     const float4* uw = &L.uw[grp * kUCap];
-    const uint8_t* um = &L.umask[grp * kUCap];
     const int8_t* us = &B.uslot[grp * kUCap];
-    for (int e = 0; e < nu; ++e) {
+    // a pixel that did not select the row has weight 0: multiplied rather
+    // than branched over (fewer instructions than testing its mask bit)
+    auto row_grad = [&](int e, float& a0, float& a1) {
       const float4 w = uw[e];
-      const float ws[kPG] = {w.x, w.y, w.z, w.w};
-      const uint32_t mk = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(um[e]));
-      const int s = __builtin_amdgcn_readfirstlane(static_cast<int>(us[e]));
-      float a0 = 0.f, a1 = 0.f;
-#pragma unroll
-      for (int q = 0; q < kPG; ++q) {
-        if (!(mk & (1u << q))) continue;
-        a0 += ws[q] * g0[q];
-        a1 += ws[q] * g1[q];
-      }
-      const int g = s >= 0 ? 0 : __builtin_amdgcn_readfirstlane(ug[e]);
-      add_feature_grad(B, gg, s, g, lane, cb, dim, a0, a1);
+      a0 = w.x * g0[0] + w.y * g0[1] + w.z * g0[2] + w.w * g0[3];
+      a1 = w.x * g1[0] + w.y * g1[1] + w.z * g1[2] + w.w * g1[3];
+    };
+    // Rows are summed into their slot's registers two at a time (their LDS
+    // reads issued together); a row without a slot lands in the unused
+    // register kSlotCap and goes to global memory after the loop, so that
+    // the loop issues no memory operation (and so waits for none).
+    int e = 0;
+    for (; e + 2 <= nu; e += 2) {
+      const int sa = __builtin_amdgcn_readfirstlane(static_cast<int>(us[e]));
+      const int sb = __builtin_amdgcn_readfirstlane(static_cast<int>(us[e + 1]));
+      float a0, a1, b0, b1;
+      row_grad(e, a0, a1);
+      row_grad(e + 1, b0, b1);
+      acc0[sa] += a0;
+      acc1[sa] += a1;
+      acc0[sb] += b0;
+      acc1[sb] += b1;
+    }
+    if (e < nu) {
+      const int sa = __builtin_amdgcn_readfirstlane(static_cast<int>(us[e]));
+      float a0, a1;
+      row_grad(e, a0, a1);
+      acc0[sa] += a0;
+      acc1[sa] += a1;
+    }
+    uint32_t deferred = __builtin_amdgcn_readfirstlane(B.udefer[grp]);
+    while (deferred) {
+      const int e = __builtin_ctz(deferred);
+      deferred &= deferred - 1u;
+      float a0, a1;
+      row_grad(e, a0, a1);
+      add_feature_grad(gg, -1, __builtin_amdgcn_readfirstlane(ug[e]), lane, cb, dim, a0, a1, acc0, acc1);
     }
   } else {
 #pragma unroll
@@ -288,14 +355,17 @@ __device__ __forceinline__ void group_feature_grads(const GView& v, const GGrad&
         const int s = slot_of(B, pos - lo);
         const int g = s >= 0 ? 0 : static_cast<int>(__builtin_amdgcn_readfirstlane(v.sorted_gid[pos]));
         const float w = s_sel_w[p * KP + j] * inv;
-        add_feature_grad(B, gg, s, g, lane, cb, dim, w * g0[q], w * g1[q]);
+        add_feature_grad(gg, s, g, lane, cb, dim, w * g0[q], w * g1[q], acc0, acc1);
       }
     }
   }
 }
 
-// Backward of one tile (all 256 threads of the workgroup).
-template <int DT>
+// Backward of one tile (all 256 threads of the workgroup). kBatch: groups
+// whose rows of dL/d(out) are requested together in the feature pass;
+// kAhead: the next batch is requested while one is summed (more round trips
+// overlap, at the cost of registers).
+template <int DT, int kBatch, bool kAhead>
 __device__ __forceinline__ void quantile_backward_tile(const GView& v, const GGrad& gg, int tile,
                                                        int K, int dim, const qr_params& prm,
                                                        QuantileLds& L, BwdLds& B,
@@ -305,7 +375,7 @@ __device__ __forceinline__ void quantile_backward_tile(const GView& v, const GGr
   const int tiles_x = (v.W + kTile - 1) / kTile;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: row addresses stay scalar
   constexpr int kWaveGroups = kGroups / 4;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int px = tx * kTile + (tid % kTile);
@@ -341,7 +411,7 @@ __device__ __forceinline__ void quantile_backward_tile(const GView& v, const GGr
     B.bpre[tid] = incl - c;
     if (tid == kPosCap / 32 - 1) B.nslot = min(incl, kSlotCap);
   }
-  for (int i = tid; i < kSlotCap * kGeo; i += kTilePix) B.geo[i] = 0.f;
+  for (int i = tid; i < 4 * kSlotCap * kGeo; i += kTilePix) (&B.geo[0][0])[i] = 0.f;
   for (int i = tid; i < kSlotCap * kChunk; i += kTilePix) B.acc[i] = 0.f;
   __syncthreads();
   for (int j = 0; j < ns; ++j) {
@@ -351,16 +421,19 @@ __device__ __forceinline__ void quantile_backward_tile(const GView& v, const GGr
   if (lane < kWaveGroups) {
     const int grp = wave * kWaveGroups + lane;
     const int nu = L.unum[grp];
-    for (int e = 0; e < nu; ++e)
-      B.uslot[grp * kUCap + e] = static_cast<int8_t>(slot_of(B, B.upos[grp * kUCap + e] - lo));
+    uint32_t defer = 0u;
+    for (int e = 0; e < nu; ++e) {
+      const int sl = slot_of(B, B.upos[grp * kUCap + e] - lo);
+      B.uslot[grp * kUCap + e] = static_cast<int8_t>(sl >= 0 ? sl : kSlotCap);
+      if (sl < 0) defer |= 1u << e;
+    }
+    B.udefer[grp] = defer;
   }
   __syncthreads();
   const int nslot = B.nslot;
 
   if (geo) {
-    // ---- dots d_pj (wave-local) ----
-    for (int j = 0; j < KP; ++j) s_d[tid * KP + j] = 0.f;
-    wave_lds_sync();
+    // ---- dots d_pj (wave-local; the first pass stores every selection's) ----
     for (int gl = 0; gl < kWaveGroups; ++gl) {
       const int grp = wave * kWaveGroups + gl;
       const int nu = __builtin_amdgcn_readfirstlane(L.unum[grp]);
@@ -395,7 +468,7 @@ __device__ __forceinline__ void quantile_backward_tile(const GView& v, const GGr
         const int s = slot_of(B, my_pos[j] - lo);
         if (s >= 0) {
 #pragma unroll
-          for (int i = 0; i < kGeo; ++i) atomicAdd(&B.geo[s * kGeo + i], gv[i]);
+          for (int i = 0; i < kGeo; ++i) atomicAdd(&B.geo[wave][s * kGeo + i], gv[i]);
         } else {
           if (gg.grad_co)
             for (int i = 0; i < 4; ++i) atomic_add(gg.grad_co + 4 * g + i, gv[i]);
@@ -406,7 +479,7 @@ __device__ __forceinline__ void quantile_backward_tile(const GView& v, const GGr
     }
     __syncthreads();
     for (int i = tid; i < nslot * kGeo; i += kTilePix) {
-      const float val = B.geo[i];
+      const float val = B.geo[0][i] + B.geo[1][i] + B.geo[2][i] + B.geo[3][i];
       const int s = i / kGeo, k = i - s * kGeo;
       const int g = B.sgid[s];
       if (val == 0.f) continue;
@@ -420,19 +493,56 @@ __device__ __forceinline__ void quantile_backward_tile(const GView& v, const GGr
 
   if (gg.grad_features) {
     // ---- feature gradients, one chunk of columns at a time ----
+    // Each wave sums its groups' rows per slot in registers, the four waves'
+    // sums meet in LDS, and one atomic per (slot, column) goes to memory.
     for (int cb = 0; cb < dim; cb += kChunk) {
-      for (int gl = 0; gl < kWaveGroups; ++gl) {
-        const int grp = wave * kWaveGroups + gl;
-        const int nu = __builtin_amdgcn_readfirstlane(L.unum[grp]);
-        group_feature_grads(v, gg, L, B, s_sel_pos, s_sel_w, KP, grp, nu, lo, tx, ty, lane, cb, dim);
+      float acc0[kAccRegs], acc1[kAccRegs];  // [kSlotCap]: rows without a slot
+#pragma unroll
+      for (int i = 0; i < kAccRegs; ++i) {
+        acc0[i] = 0.f;
+        acc1[i] = 0.f;
+      }
+      // rows of dL/d(out) are requested kBatch groups at a time (one batch
+      // ahead of the batch being summed if kAhead)
+      constexpr int kNB = kWaveGroups / kBatch;
+      float gA0[kBatch][kPG], gA1[kBatch][kPG], gB0[kBatch][kPG], gB1[kBatch][kPG];
+      if (kAhead) load_grad_batch<kBatch>(v, gg, wave, lane, tx, ty, cb, dim, 0, gA0, gA1);
+#pragma unroll 1
+      for (int h = 0; h < kNB; ++h) {
+        if (!kAhead) {
+          load_grad_batch<kBatch>(v, gg, wave, lane, tx, ty, cb, dim, h, gA0, gA1);
+        } else if (h + 1 < kNB) {
+          load_grad_batch<kBatch>(v, gg, wave, lane, tx, ty, cb, dim, h + 1, gB0, gB1);
+          // batch h has arrived once at most the next batch's loads are
+          // outstanding
+          wait_vmcnt<kGradBatchLoads<kBatch>>();
+        }
+#pragma unroll
+        for (int gi = 0; gi < kBatch; ++gi)
+          group_feature_grads(v, gg, L, B, s_sel_pos, s_sel_w, KP, wave * kWaveGroups + h * kBatch + gi,
+                              lo, lane, cb, dim, gA0[gi], gA1[gi], acc0, acc1);
+        if (kAhead) {
+#pragma unroll
+          for (int gi = 0; gi < kBatch; ++gi) {
+#pragma unroll
+            for (int q = 0; q < kPG; ++q) {
+              gA0[gi][q] = gB0[gi][q];
+              gA1[gi][q] = gB1[gi][q];
+            }
+          }
+        }
+      }
+      for (int i = 0; i < nslot; ++i) {
+        atomicAdd(&B.acc[i * kChunk + lane], acc0[i]);
+        atomicAdd(&B.acc[i * kChunk + 64 + lane], acc1[i]);
       }
       __syncthreads();
       for (int i = tid; i < nslot * kChunk; i += kTilePix) {
-        const int s = i / kChunk, c = i - s * kChunk;
+        const int sl = i / kChunk, c = i - sl * kChunk;
         const float val = B.acc[i];
         B.acc[i] = 0.f;
         if (val != 0.f && cb + c < dim)
-          atomic_add(gg.grad_features + static_cast<int64_t>(B.sgid[s]) * dim + cb + c, val);
+          atomic_add(gg.grad_features + static_cast<int64_t>(B.sgid[sl]) * dim + cb + c, val);
       }
       __syncthreads();
     }
@@ -455,7 +565,7 @@ quantile_backward_kernel(ViewArgs v, GradPtrs gp, int n_tiles, qr_params prm, in
   int* s_sel_pos = reinterpret_cast<int*>(dyn_lds);
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + n;
   float* s_d = s_sel_w + n;
-  quantile_backward_tile<DT>(to_global(v), to_global(gp), xcd_remap(blockIdx.x, n_tiles), K, dim,
+  quantile_backward_tile<DT, 2, true>(to_global(v), to_global(gp), xcd_remap(blockIdx.x, n_tiles), K, dim,
                              prm, L, B, s_sel_pos, s_sel_w, s_d);
 }
 
@@ -480,7 +590,7 @@ quantile_backward_batched_grid_kernel(const qr_view* __restrict__ views,
   float* s_d = s_sel_w + n;
   const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[xcd_remap(blockIdx.x, n_items)]);
   const uint32_t vi = packed >> kViewShift;
-  quantile_backward_tile<DT>(to_global(view_args(views[vi])), to_global(grad_ptrs(grads[vi])),
+  quantile_backward_tile<DT, 1, true>(to_global(view_args(views[vi])), to_global(grad_ptrs(grads[vi])),
                              static_cast<int>(packed & kTileMask), K, dim, prm, L, B, s_sel_pos,
                              s_sel_w, s_d);
 }
@@ -530,7 +640,7 @@ quantile_backward_batched_kernel(const qr_view* __restrict__ views,
     if (item >= n_items) break;
     const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[item]);
     const uint32_t vi = packed >> kViewShift;
-    quantile_backward_tile<DT>(to_global(view_args(views[vi])), to_global(grad_ptrs(grads[vi])),
+    quantile_backward_tile<DT, 1, false>(to_global(view_args(views[vi])), to_global(grad_ptrs(grads[vi])),
                                static_cast<int>(packed & kTileMask), K, dim, prm, L, B, s_sel_pos,
                                s_sel_w, s_d);
   }
