@@ -104,20 +104,18 @@ struct PixelSel {
   float TQ;  // T^Q after the last selection
 };
 
-// Runs the walk and the merge for one tile (all 256 threads of the
-// workgroup). Selections go to s_sel_pos / s_sel_w ([256][KP], as absolute
-// positions in sorted_gid and w^Q); L receives ns (-1 outside the image),
-// 1 / (1 - T^Q) and the merged groups with Gaussian ids; if upos is given it
-// receives the merged groups' list positions ([kGroups][kUCap]). Workgroup barriers
-// occur only around the staging of record batches; the record batch is only
-// rewritten after a barrier that every wave reaches once it has finished the
-// previous tile.
-__device__ __forceinline__ PixelSel quantile_select(const GView& v, int lo, int hi, int K,
-                                                    float pxc, float pyc, bool inside,
-                                                    const qr_params& prm, QuantileLds& L,
-                                                    int* __restrict__ s_sel_pos,
-                                                    float* __restrict__ s_sel_w, int KP,
-                                                    int* __restrict__ upos = nullptr) {
+// The walk for one tile (all 256 threads of the workgroup). Selections go to
+// s_sel_pos / s_sel_w ([256][KP], as absolute positions in sorted_gid and
+// w^Q); L (any LDS struct with the staging arrays mean, co, the thresholds
+// thr and the per-pixel ns, inv) receives ns (-1 outside the image) and
+// 1 / (1 - T^Q). Workgroup barriers occur only around the staging of record
+// batches; the record batch is only rewritten after a barrier that every
+// wave reaches once it has finished the previous tile.
+template <class WalkLds>
+__device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi, int K, float pxc,
+                                                  float pyc, bool inside, const qr_params& prm,
+                                                  WalkLds& L, int* __restrict__ s_sel_pos,
+                                                  float* __restrict__ s_sel_w, int KP) {
   const int tid = threadIdx.x;
   // thr[k] = t_{k+1}; thr[K] = 0 (identical for every tile of a launch)
   if (tid <= K) L.thr[tid] = quantile_threshold(tid + 1, K);
@@ -180,6 +178,14 @@ __device__ __forceinline__ PixelSel quantile_select(const GView& v, int lo, int 
   L.inv[tid] = ns > 0 ? 1.f / (1.f - TQ) : 0.f;
   wave_lds_sync();
 
+  return PixelSel{ns, TQ};
+}
+
+// The merge for one tile (all 256 threads; wave-local), after the walk.
+__device__ __forceinline__ void merge_groups(const GView& v, QuantileLds& L,
+                                             const int* __restrict__ s_sel_pos,
+                                             const float* __restrict__ s_sel_w, int KP) {
+  const int tid = threadIdx.x;
   // The merge, wave-local: adjacent pixels select mostly the same
   // Gaussians, so a group's distinct selections are far fewer than its
   // pixels' selections. Lane l < 16 merges group 16 w + l.
@@ -236,15 +242,21 @@ __device__ __forceinline__ PixelSel quantile_select(const GView& v, int lo, int 
 #pragma unroll
     for (int e = 0; e < kUCap; ++e) gid[e] = pos[e] >= 0 ? v.sorted_gid[pos[e]] : 0u;
 #pragma unroll
-    for (int e = 0; e < kUCap; ++e) {
-      if (e < cnt) {
-        L.ugid[grp * kUCap + e] = static_cast<int>(gid[e]);
-        if (upos) upos[grp * kUCap + e] = pos[e];
-      }
-    }
+    for (int e = 0; e < kUCap; ++e)
+      if (e < cnt) L.ugid[grp * kUCap + e] = static_cast<int>(gid[e]);
   }
   wave_lds_sync();
-  return PixelSel{ns, TQ};
+}
+
+// Walk and merge (the forward renderer's selection phase).
+__device__ __forceinline__ PixelSel quantile_select(const GView& v, int lo, int hi, int K,
+                                                    float pxc, float pyc, bool inside,
+                                                    const qr_params& prm, QuantileLds& L,
+                                                    int* __restrict__ s_sel_pos,
+                                                    float* __restrict__ s_sel_w, int KP) {
+  const PixelSel sel = quantile_walk(v, lo, hi, K, pxc, pyc, inside, prm, L, s_sel_pos, s_sel_w, KP);
+  merge_groups(v, L, s_sel_pos, s_sel_w, KP);
+  return sel;
 }
 
 }  // namespace qr
