@@ -112,7 +112,7 @@ __device__ __forceinline__ void load_feat8(const GView& v, int64_t g, int dim, i
 constexpr int kSlots = 32;      // distinct selections of a tile given slots
 constexpr int kPosCap = 2048;   // list positions covered by the slot bitmap
 constexpr int kGeo = 6;         // d/d(a, b, c, o, u, v)
-constexpr int kNB = 8;          // 16-column MFMA blocks per wave and round
+constexpr int kNB = 4;          // 16-column MFMA blocks per wave and round
 
 // LDS of the backward (the walk's staging and per-pixel scalars, then the
 // slot map and the geometric sums).
@@ -145,8 +145,16 @@ __device__ __forceinline__ const QR_GLOBAL float* grad_row(const GView& v, const
   return gg.grad_out + (static_cast<int64_t>(gy) * v.W + gx) * dim;
 }
 
+// Raw operands of one 32-column step of slot_dots.
+struct DotStep {
+  f32x4 a[4][2];  // g_p, columns c .. c+7, of the lane's pixel in each 16-pixel block
+  float f[2][8];  // f_s, columns c .. c+7, of the lane's slot in each 16-slot block
+};
+
 // D[p][s] = <g_p, f_s> for the wave's 64 pixels and the tile's slots, stored
-// to s_d at the place of slot s in pixel p's selection list.
+// to s_d at the place of slot s in pixel p's selection list. The operands of
+// step k+1 are requested before step k is multiplied (a fixed number of
+// loads per step, every address clamped into range).
 template <int DT>
 __device__ __forceinline__ void slot_dots(const GView& v, const GGrad& gg, const BwdLds& B,
                                           int nslot, int tx, int ty, int wave, int lane, int dim,
@@ -164,25 +172,32 @@ __device__ __forceinline__ void slot_dots(const GView& v, const GGrad& gg, const
   for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < dim; k0 += 32) {
-    const int c = k0 + kq;  // this lane's 8 columns (dim is a multiple of 8)
-    const bool live = c < dim;
+  const int nk = (dim + 31) >> 5;
+  auto load = [&](int k, DotStep& o) {
+    const int c = min(k * 32 + kq, dim - 8);  // dim is a multiple of 8
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      o.a[mb][0] = __builtin_nontemporal_load(reinterpret_cast<const QR_GLOBAL f32x4*>(arow[mb] + c));
+      o.a[mb][1] = __builtin_nontemporal_load(reinterpret_cast<const QR_GLOBAL f32x4*>(arow[mb] + c + 4));
+    }
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) load_feat8<DT>(v, gid[nb], dim, c, o.f[nb]);
+  };
+  auto multiply = [&](int k, const DotStep& o) {
+    const bool live = k * 32 + kq < dim;  // columns past dim contribute zero
     bf16x8 ahi[4], alo[4], bhi[2], blo[2];
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
       float x[8];
-      const f32x4 a0 = live ? *reinterpret_cast<const QR_GLOBAL f32x4*>(arow[mb] + c) : f32x4{0.f, 0.f, 0.f, 0.f};
-      const f32x4 a1 = live ? *reinterpret_cast<const QR_GLOBAL f32x4*>(arow[mb] + c + 4) : f32x4{0.f, 0.f, 0.f, 0.f};
-      x[0] = a0.x; x[1] = a0.y; x[2] = a0.z; x[3] = a0.w;
-      x[4] = a1.x; x[5] = a1.y; x[6] = a1.z; x[7] = a1.w;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        x[i] = live ? o.a[mb][0][i] : 0.f;
+        x[4 + i] = live ? o.a[mb][1][i] : 0.f;
+      }
       split8(x, ahi[mb], alo[mb]);
     }
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
-      float f[8];
-      load_feat8<DT>(v, gid[nb], dim, live ? c : 0, f);
-      split8(f, bhi[nb], blo[nb]);
-    }
+    for (int nb = 0; nb < 2; ++nb) split8(o.f[nb], bhi[nb], blo[nb]);
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
       if (nb >= n_nb) continue;
@@ -194,6 +209,14 @@ __device__ __forceinline__ void slot_dots(const GView& v, const GGrad& gg, const
           acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mb], blo[nb], acc[mb][nb], 0, 0, 0);
       }
     }
+  };
+  DotStep X, Y;
+  load(0, X);
+  for (int k = 0; k < nk; k += 2) {
+    load(min(k + 1, nk - 1), Y);
+    multiply(k, X);
+    load(min(k + 2, nk - 1), X);
+    if (k + 1 < nk) multiply(k + 1, Y);
   }
   // accumulator layout: lane holds D[4 (lane / 16) + i][lane % 16]
 #pragma unroll
@@ -212,8 +235,9 @@ __device__ __forceinline__ void slot_dots(const GView& v, const GGrad& gg, const
 }
 
 // dF[s][c] = sum_p (w_ps / Z_p) g_p[c] for the tile's slots and this wave's
-// column blocks (16-column block b belongs to wave b % 4), added to
-// grad_features.
+// column blocks (16-column block b belongs to wave b % 4, kNB of them per
+// round), added to grad_features. The dL/d(out) operand of step k+1 is
+// requested before step k is multiplied.
 __device__ __forceinline__ void slot_feature_grads(const GView& v, const GGrad& gg, const BwdLds& B,
                                                    const float* __restrict__ s_sel_w, int nslot,
                                                    int tx, int ty, int wave, int lane, int dim,
@@ -221,14 +245,27 @@ __device__ __forceinline__ void slot_feature_grads(const GView& v, const GGrad& 
   const int row = lane & 15, kq = (lane >> 4) * 8;
   const int n_mb = (nslot + 15) >> 4;
   const int n_blk = dim >> 4;
-  for (int b0 = wave; b0 < n_blk; b0 += 4 * kNB) {  // up to kNB of this wave's blocks per round
+  constexpr int kSteps = kTilePix / 32;
+  for (int b0 = wave; b0 < n_blk; b0 += 4 * kNB) {
     floatx4 acc[2][kNB];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
       for (int nb = 0; nb < kNB; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < kTilePix; k0 += 32) {
-      // A = W^T: slot mb * 16 + row, pixels k0 + kq .. k0 + kq + 7
+    int col[kNB];
+#pragma unroll
+    for (int nb = 0; nb < kNB; ++nb) col[nb] = min(b0 + 4 * nb, n_blk - 1) * 16 + row;  // clamped
+    // B = G: pixels k*32 + kq .. + 7, column col[nb]
+    auto load = [&](int k, float (&x)[kNB][8]) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const QR_GLOBAL float* r = grad_row(v, gg, tx, ty, k * 32 + kq + t, dim);
+#pragma unroll
+        for (int nb = 0; nb < kNB; ++nb) x[nb][t] = __builtin_nontemporal_load(r + col[nb]);
+      }
+    };
+    auto multiply = [&](int k, const float (&x)[kNB][8]) {
+      // A = W^T: slot mb * 16 + row, pixels k*32 + kq .. + 7
       bf16x8 ahi[2], alo[2];
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb) {
@@ -236,24 +273,16 @@ __device__ __forceinline__ void slot_feature_grads(const GView& v, const GGrad& 
         float w[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-          const int p = k0 + kq + t;
+          const int p = k * 32 + kq + t;
           const uint32_t m = B.smask[p];
           w[t] = ((m >> sl) & 1u) ? s_sel_w[p * KP + __popc(m & ((1u << sl) - 1u))] * B.inv[p] : 0.f;
         }
         split8(w, ahi[mb], alo[mb]);
       }
-      // B = G: pixels k0 + kq .. + 7, column (block) * 16 + row
 #pragma unroll
       for (int nb = 0; nb < kNB; ++nb) {
-        const int blk = b0 + 4 * nb;
-        if (blk >= n_blk) continue;
-        const int col = blk * 16 + row;
-        float x[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-          x[t] = __builtin_nontemporal_load(grad_row(v, gg, tx, ty, k0 + kq + t, dim) + col);
         bf16x8 bhi, blo;
-        split8(x, bhi, blo);
+        split8(x[nb], bhi, blo);
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
           if (mb >= n_mb) continue;
@@ -262,6 +291,15 @@ __device__ __forceinline__ void slot_feature_grads(const GView& v, const GGrad& 
           acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mb], blo, acc[mb][nb], 0, 0, 0);
         }
       }
+    };
+    float X[kNB][8], Y[kNB][8];
+    load(0, X);
+#pragma unroll 1
+    for (int k = 0; k < kSteps; k += 2) {
+      load(k + 1, Y);
+      multiply(k, X);
+      load(min(k + 2, kSteps - 1), X);
+      multiply(k + 1, Y);
     }
     // lane holds dF[4 (lane / 16) + i][lane % 16] of each block
 #pragma unroll
