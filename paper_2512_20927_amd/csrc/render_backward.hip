@@ -17,8 +17,6 @@
 //    dpower/du = a dx + b dy, /dv = b dx + c dy.
 // Per-tile partial sums are accumulated into the caller's gradient arrays
 // with float32 atomics.
-#include <algorithm>
-
 #include "common.h"
 #include "render_common.h"
 
@@ -28,7 +26,7 @@ constexpr int kCW = 32;          // feature columns staged per chunk
 constexpr int kGStride = kCW + 1;  // LDS row stride of the grad_out chunk
 
 // Loads the [256 px x kCW] slice [c0, c0 + kCW) of the tile's grad_out into
-// LDS (rows of pixels outside the image are zero).
+// LDS (rows of pixels outside the image, and columns past dim, are zero).
 __device__ __forceinline__ void load_grad_chunk(float* s_g, const QR_GLOBAL float* __restrict__ grad_out,
                                                 int W, int H, int tx, int ty, int dim, int c0) {
   constexpr int per_row = kCW / 4;
@@ -45,22 +43,47 @@ __device__ __forceinline__ void load_grad_chunk(float* s_g, const QR_GLOBAL floa
 
 // ============================================================================
 // Dense backward. One workgroup per tile, one thread per pixel; the list is
-// walked front to back in batches of 16 entries exactly as in the forward.
-// For each batch, over grad_out chunks staged in LDS:
-//   d_pj = <g_p, f_j> (thread per pixel) and
-//   dL/df_j = sum_p w_pj g_p (thread per (entry, column) pair),
+// walked front to back in batches of 32 entries exactly as in the forward.
+// For each batch, over 32-column chunks of grad_out staged in LDS, two
+// contractions on v_mfma_f32_16x16x32_bf16 (float32 operands split into
+// bfloat16 pairs, hi.hi + hi.lo + lo.hi, float32 accumulation):
+//   D  = G F^T  [256 px x 32 entries], the dots d_pj = <g_p, f_j> (each wave
+//        its 64 pixels, accumulated over the chunks);
+//   dF = W^T G  [32 entries x 32 columns] per chunk, W[p][j] = T_pj alpha'_pj
+//        (each wave one 16 x 16 block over all 256 pixels), added to
+//        grad_features with one atomic per (entry, column);
 // then dL/dalpha'_pj uses the prefix sum_{l<=j} w_l d_l against the whole-ray
 // total <g_p, out_p>, and each entry's geometric gradient is summed over the
 // tile's pixels by wave reductions before one atomic per value.
-constexpr int kDB = 16;  // list entries per batch
+constexpr int kDB = 32;            // list entries per batch (= MFMA K / N)
+constexpr int kWS = kTilePix + 1;  // LDS stride of an entry's weights
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ float wave_sum(float v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
+__device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const __bf16 h = static_cast<__bf16>(x[i]);
+    hi[i] = h;
+    lo[i] = static_cast<__bf16>(x[i] - static_cast<float>(h));
+  }
+}
+
+__device__ __forceinline__ void mfma3(floatx4& acc, const bf16x8& ahi, const bf16x8& alo,
+                                      const bf16x8& bhi, const bf16x8& blo) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc, 0, 0, 0);
+}
+
 template <int DT>
-__global__ void __launch_bounds__(kTilePix)
+__global__ void __launch_bounds__(kTilePix, 2)
 dense_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
                       const uint32_t* __restrict__ tile_offsets,
                       const uint32_t* __restrict__ sorted_gid, const float2* __restrict__ means2d,
@@ -71,18 +94,21 @@ dense_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
   const QR_GLOBAL void* gfeats = (const QR_GLOBAL void*)feats;
   const QR_GLOBAL float* gscale = (const QR_GLOBAL float*)scale;
   const QR_GLOBAL float* ggrad = (const QR_GLOBAL float*)grad_out;
-  __shared__ float s_g[kTilePix * kGStride];
-  __shared__ float s_f[kDB * kCW];
-  __shared__ float s_w[kDB][kTilePix + 1];  // +1: entries land in distinct banks
-  __shared__ float s_T[kDB][kTilePix];
+  QR_GLOBAL float* ggf = (QR_GLOBAL float*)grad_features;
+  __shared__ float s_g[kTilePix * kGStride];  // grad_out chunk; later the batch's dots [kDB][kWS]
+  __shared__ float s_f[kDB * kGStride];       // feature chunk [entry][column]
+  __shared__ float s_w[kDB * kWS];            // weights [entry][pixel]
   __shared__ float2 s_mean[kDB];
   __shared__ float4 s_co[kDB];
   __shared__ int s_gid[kDB];
   __shared__ float s_red[4][6];
   __shared__ float s_tot[kTilePix];
+  static_assert(kDB * kWS <= kTilePix * kGStride, "dots must fit in the grad_out chunk space");
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int row = lane & 15, kq = (lane >> 4) * 8;
   const int tile = xcd_remap(blockIdx.x, n_tiles);
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int px = tx * kTile + (tid % kTile);
@@ -123,10 +149,10 @@ dense_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
       s_co[tid] = conic_opacity[g];
     }
     __syncthreads();
-    // forward walk of the batch: weights and the T before each entry
+    // forward walk of the batch: this pixel's weights (0 off the ray, after
+    // the stop and past the list end)
     for (int j = 0; j < kDB; ++j) {
       float w = 0.f;
-      s_T[j][tid] = T;
       if (j < cnt && !done) {
         const float alpha = gauss_alpha(s_mean[j], s_co[j], pxc, pyc, prm.alpha_max);
         if (alpha >= prm.alpha_min) {
@@ -139,66 +165,98 @@ dense_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
           }
         }
       }
-      s_w[j][tid] = w;
+      s_w[j * kWS + tid] = w;
     }
-    float d[kDB];
+    floatx4 dacc[4][2];
 #pragma unroll
-    for (int j = 0; j < kDB; ++j) d[j] = 0.f;
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) dacc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int c0 = 0; c0 < dim; c0 += kCW) {
-      __syncthreads();
+      __syncthreads();  // previous chunk consumed (and the weights written)
       load_grad_chunk(s_g, ggrad, W, H, tx, ty, dim, c0);
-      for (int e = tid; e < kDB * (kCW / 4); e += kTilePix) {
-        const int j = e / (kCW / 4), c4 = e - j * (kCW / 4);
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (j < cnt && c0 + 4 * c4 < dim) v = load_feat4_global<DT>(gfeats, gscale, s_gid[j], dim, c0 + 4 * c4);
-        *reinterpret_cast<float4*>(&s_f[j * kCW + 4 * c4]) = v;
+      {  // feature chunk: entry tid / 8, four columns each
+        const int j = tid >> 3, c4 = tid & 7;
+        float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (j < cnt && c0 + 4 * c4 < dim) f = load_feat4_global<DT>(gfeats, gscale, s_gid[j], dim, c0 + 4 * c4);
+        float* r = s_f + j * kGStride + 4 * c4;
+        r[0] = f.x; r[1] = f.y; r[2] = f.z; r[3] = f.w;
       }
       __syncthreads();
-      // dots for this pixel over the chunk
-      const float* gr = s_g + tid * kGStride;
-#pragma unroll 1
-      for (int c = 0; c < kCW; c += 4) {
-        const float g0 = gr[c], g1 = gr[c + 1], g2 = gr[c + 2], g3 = gr[c + 3];
+      // dots: A = G (pixel wave*64 + mb*16 + row, columns kq..kq+7),
+      //       B = F^T (columns kq..kq+7, entry nb*16 + row)
+      {
+        bf16x8 bhi[2], blo[2];
 #pragma unroll
-        for (int j = 0; j < kDB; ++j) {
-          const float4 f = *reinterpret_cast<const float4*>(&s_f[j * kCW + c]);
-          d[j] += g0 * f.x + g1 * f.y + g2 * f.z + g3 * f.w;
+        for (int nb = 0; nb < 2; ++nb) {
+          float x[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) x[i] = s_f[(nb * 16 + row) * kGStride + kq + i];
+          split8(x, bhi[nb], blo[nb]);
+        }
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          float x[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) x[i] = s_g[(wave * 64 + mb * 16 + row) * kGStride + kq + i];
+          bf16x8 ahi, alo;
+          split8(x, ahi, alo);
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) mfma3(dacc[mb][nb], ahi, alo, bhi[nb], blo[nb]);
         }
       }
-      // feature gradients: thread -> (entry j, two columns), summed over pixels
+      // feature gradients of this chunk: wave w computes the 16 x 16 block
+      // (entries 16 (w / 2) .., columns 16 (w % 2) ..) over all pixels
       if (grad_features) {
-        const int j = tid >> 4;          // 16 entries
-        const int cb = (tid & 15) * 2;   // 2 columns each
-        if (j < cnt && c0 + cb < dim) {
-          float a0 = 0.f, a1 = 0.f;
-          for (int p = 0; p < kTilePix; ++p) {
-            const float w = s_w[j][p];
-            a0 += w * s_g[p * kGStride + cb];
-            a1 += w * s_g[p * kGStride + cb + 1];
+        const int e0 = (wave >> 1) * 16, n0 = (wave & 1) * 16;
+        floatx4 facc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+        for (int k0 = 0; k0 < kTilePix; k0 += 32) {
+          float a[8], b[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            a[i] = s_w[(e0 + row) * kWS + k0 + kq + i];
+            b[i] = s_g[(k0 + kq + i) * kGStride + n0 + row];
           }
-          float* dst = grad_features + static_cast<int64_t>(s_gid[j]) * dim + c0 + cb;
-          if (a0 != 0.f) atomicAdd(dst, a0);
-          if (a1 != 0.f) atomicAdd(dst + 1, a1);
+          bf16x8 ahi, alo, bhi, blo;
+          split8(a, ahi, alo);
+          split8(b, bhi, blo);
+          mfma3(facc, ahi, alo, bhi, blo);
+        }
+        // lane holds dF[e0 + 4 (lane / 16) + i][n0 + lane % 16]
+        const int col = c0 + n0 + row;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j = e0 + 4 * (lane >> 4) + i;
+          if (j < cnt && col < dim && facc[i] != 0.f)
+            __hip_atomic_fetch_add(ggf + static_cast<int64_t>(s_gid[j]) * dim + col, facc[i],
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
     }
-    // park the dots in the (now free) grad_out chunk space, so that the loop
-    // below indexes them by a runtime entry number
+    // park the dots in the (now free) grad_out chunk space: s_d[entry][pixel]
     __syncthreads();
-    float* s_d = s_g;  // [kDB][kTilePix + 1]
+    float* s_d = s_g;
 #pragma unroll
-    for (int j = 0; j < kDB; ++j) s_d[j * (kTilePix + 1) + tid] = d[j];
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          s_d[(nb * 16 + row) * kWS + wave * 64 + mb * 16 + 4 * (lane >> 4) + i] = dacc[mb][nb][i];
+    __syncthreads();
     // dL/dalpha' and the geometric chain rule, reduced over the tile per entry
     for (int j = 0; j < cnt; ++j) {  // cnt is uniform across the workgroup
-      const float w = s_w[j][tid];
+      const float w = s_w[j * kWS + tid];
       float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       if (w != 0.f) {
-        const float dj = s_d[j * (kTilePix + 1) + tid];
+        const float dj = s_d[j * kWS + tid];
         prefix += w * dj;
         const AlphaEval e = eval_alpha(s_mean[j], s_co[j], pxc, pyc, prm.alpha_max);
         if (!e.clamped) {
           const float4 co = s_co[j];
-          const float dL_da = s_T[j][tid] * dj - (total - prefix) / (1.f - e.alpha);
+          const float T_before = w / e.alpha;  // w = alpha' T
+          const float dL_da = T_before * dj - (total - prefix) / (1.f - e.alpha);
           const float dpow = dL_da * e.alpha;
           v[0] = dpow * (-0.5f * e.dx * e.dx);
           v[1] = dpow * (-e.dx * e.dy);
