@@ -35,6 +35,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # sources that make up each profiled kernel (the common headers included)
 KERNEL_SOURCES = {
     "render_quantile": ["paper_2512_20927_amd/csrc/render_quantile.hip",
+                        "paper_2512_20927_amd/csrc/quantile_select.h",
                         "paper_2512_20927_amd/csrc/render_common.h",
                         "paper_2512_20927_amd/csrc/common.h"],
 }
