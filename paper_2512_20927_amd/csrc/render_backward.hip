@@ -19,6 +19,7 @@
 // with float32 atomics.
 #include "common.h"
 #include "render_common.h"
+#include "wave_ops.h"
 
 namespace qr {
 
@@ -54,33 +55,9 @@ __device__ __forceinline__ void load_grad_chunk(float* s_g, const QR_GLOBAL floa
 //        grad_features with one atomic per (entry, column);
 // then dL/dalpha'_pj uses the prefix sum_{l<=j} w_l d_l against the whole-ray
 // total <g_p, out_p>, and each entry's geometric gradient is summed over the
-// tile's pixels by wave reductions before one atomic per value.
+// tile's pixels (wave sums, then the four waves) before one atomic per value.
 constexpr int kDB = 32;            // list entries per batch (= MFMA K / N)
 constexpr int kWS = kTilePix + 1;  // LDS stride of an entry's weights
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ float wave_sum(float v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-__device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const __bf16 h = static_cast<__bf16>(x[i]);
-    hi[i] = h;
-    lo[i] = static_cast<__bf16>(x[i] - static_cast<float>(h));
-  }
-}
-
-__device__ __forceinline__ void mfma3(floatx4& acc, const bf16x8& ahi, const bf16x8& alo,
-                                      const bf16x8& bhi, const bf16x8& blo) {
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc, 0, 0, 0);
-}
 
 template <int DT>
 __global__ void __launch_bounds__(kTilePix, 2)
@@ -101,7 +78,7 @@ dense_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
   __shared__ float2 s_mean[kDB];
   __shared__ float4 s_co[kDB];
   __shared__ int s_gid[kDB];
-  __shared__ float s_red[4][6];
+  __shared__ float s_red[4][kDB][6];  // per wave, entry and value
   __shared__ float s_tot[kTilePix];
   static_assert(kDB * kWS <= kTilePix * kGStride, "dots must fit in the grad_out chunk space");
 
@@ -245,7 +222,9 @@ dense_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
         for (int i = 0; i < 4; ++i)
           s_d[(nb * 16 + row) * kWS + wave * 64 + mb * 16 + 4 * (lane >> 4) + i] = dacc[mb][nb][i];
     __syncthreads();
-    // dL/dalpha' and the geometric chain rule, reduced over the tile per entry
+    // dL/dalpha' and the geometric chain rule per (pixel, entry); each
+    // entry's six sums over a wave's pixels go to s_red, and after one
+    // barrier per batch, one atomic per (entry, value)
     for (int j = 0; j < cnt; ++j) {  // cnt is uniform across the workgroup
       const float w = s_w[j * kWS + tid];
       float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -266,23 +245,23 @@ dense_backward_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
           v[5] = dpow * (co.y * e.dx + co.z * e.dy);
         }
       }
-      // skip the reduction when no pixel of the tile blended entry j
-      if (__syncthreads_or(w != 0.f)) {
+      const bool any = __ballot(w != 0.f) != 0ull;  // uniform over the wave
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-          const float sv = wave_sum(v[q]);
-          if (lane == 0) s_red[wave][q] = sv;
-        }
-        __syncthreads();
-        if (tid < 6) {
-          const float sv = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
-          const int g = s_gid[j];
-          if (tid < 4) {
-            if (grad_co) atomicAdd(&grad_co[4 * g + tid], sv);
-          } else if (grad_means2d) {
-            atomicAdd(&grad_means2d[2 * g + tid - 4], sv);
-          }
-        }
+      for (int q = 0; q < 6; ++q) {
+        const float sv = any ? wave_sum(v[q]) : 0.f;
+        if (lane == 0) s_red[wave][j][q] = sv;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < cnt * 6; i += kTilePix) {
+      const int j = i / 6, q = i - j * 6;
+      const float sv = s_red[0][j][q] + s_red[1][j][q] + s_red[2][j][q] + s_red[3][j][q];
+      if (sv == 0.f) continue;
+      const int g = s_gid[j];
+      if (q < 4) {
+        if (grad_co) atomicAdd(&grad_co[4 * g + q], sv);
+      } else if (grad_means2d) {
+        atomicAdd(&grad_means2d[2 * g + q - 4], sv);
       }
     }
   }

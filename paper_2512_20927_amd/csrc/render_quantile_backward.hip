@@ -36,11 +36,9 @@
 // are handled by a plain wave-wide path. T^Q_j is recovered as
 // w_j / alpha'_j (alpha' >= alpha_min > 0 for every selection).
 #include "quantile_select.h"
+#include "wave_ops.h"
 
 namespace qr {
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // Gradient outputs of one view (generic pointers, host-constructible).
 struct GradPtrs {
@@ -64,40 +62,6 @@ __device__ __forceinline__ GGrad to_global(const GradPtrs& g) {
 
 __device__ __forceinline__ void atomic_add(QR_GLOBAL float* p, float v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <int kCtrl>
-__device__ __forceinline__ float dpp(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kCtrl,
-                                                               0xF, 0xF, false));
-}
-
-__device__ __forceinline__ uint32_t fbits(float x) { return __builtin_bit_cast(uint32_t, x); }
-__device__ __forceinline__ float bitsf(uint32_t x) { return __builtin_bit_cast(float, x); }
-
-// Sum over the 64 lanes, without LDS: v_permlane32_swap exchanges lanes
-// 32..63 of its first operand with lanes 0..31 of its second and
-// v_permlane16_swap odd with even 16-lane rows; DPP moves finish inside the
-// rows. Every lane returns the total.
-__device__ __forceinline__ float wave_sum(float x) {
-  const auto a = __builtin_amdgcn_permlane32_swap(fbits(x), fbits(x), false, false);
-  float k = bitsf(a[0]) + bitsf(a[1]);  // both halves: x(l) + x(l ^ 32)
-  const auto b = __builtin_amdgcn_permlane16_swap(fbits(k), fbits(k), false, false);
-  k = bitsf(b[0]) + bitsf(b[1]);
-  k += dpp<0xB1>(k);   // quad_perm [1,0,3,2]
-  k += dpp<0x4E>(k);   // quad_perm [2,3,0,1]
-  k += dpp<0x124>(k);  // row_ror:4
-  k += dpp<0x128>(k);  // row_ror:8
-  return k;
-}
-
-__device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const __bf16 h = static_cast<__bf16>(x[i]);
-    hi[i] = h;
-    lo[i] = static_cast<__bf16>(x[i] - static_cast<float>(h));
-  }
 }
 
 // Eight consecutive decoded features (columns c .. c+7) of Gaussian g.
