@@ -131,6 +131,31 @@ def test_backward_ragged_small_dim(qr, K):
     _run(qr, sc, cam, K, seed=K)
 
 
+def test_backward_selections_past_position_2048(qr):
+    """The first tile's list starts with 2,400 small Gaussians clustered on a
+    few pixels of its corner, in front of 40 large ones: the other pixels of
+    the tile select large Gaussians beyond list position 2,048, outside the
+    backward's slot bitmap, which take the per-selection path (K = 32)."""
+    rng = np.random.default_rng(17)
+    n_small, n_big, dim = 2400, 40, 48
+    n = n_small + n_big
+    means = np.zeros((n, 3), np.float32)
+    means[:n_small, :2] = rng.uniform(-0.97, -0.90, (n_small, 2))  # about pixel (3, 3)
+    means[:n_small, 2] = -1.0 + rng.uniform(0.0, 0.01, n_small)    # depth about 2
+    means[n_small:, :2] = rng.uniform(-2.0, 2.0, (n_big, 2))
+    means[n_small:, 2] = 1.0 + rng.uniform(0.0, 0.5, n_big)         # depth 4 to 4.5
+    scales = np.concatenate([np.full((n_small, 3), 0.004, np.float32),
+                             rng.uniform(0.15, 0.4, (n_big, 3)).astype(np.float32)])
+    quats = rng.standard_normal((n, 4)).astype(np.float32)
+    opacity = np.concatenate([np.full(n_small, 0.9, np.float32),
+                              rng.uniform(0.3, 0.7, n_big).astype(np.float32)])
+    sc = synth.Scene(means, scales, quats, opacity, rng.standard_normal((n, dim)).astype(np.float32))
+    cam = synth.tiny_camera(32)
+    _, _, _, _, host, _ = _setup(qr, sc, cam)
+    assert np.diff(host["offs"]).max() > 2048
+    _run(qr, sc, cam, 32, seed=3)
+
+
 @pytest.mark.parametrize("storage", ["bf16", "fp8"])
 def test_backward_reduced_precision_storage(qr, storage):
     sc, cam = synth.make_fd_case(seed=6, n=1500)
