@@ -91,6 +91,13 @@ typedef struct qr_params {
   float T_eps;
   float dilation;
   float guard;
+  /* Element type of the feature maps the Q-Render forward writes (`out` of
+   * qr_render_quantile and of every qr_view of qr_render_quantile_batched):
+   * QR_F32 (0, default) or QR_BF16 (round to nearest even from the float32
+   * result; `out` then points to u16 codes). The dense blend writes
+   * float32 only (QR_ERR_UNSUPPORTED otherwise); the backward passes ignore
+   * it. */
+  int32_t out_dtype;
 } qr_params;
 
 /* One view of a batched render (qr_render_quantile_batched). All pointers are

@@ -64,7 +64,7 @@ class qr_view_grad(ctypes.Structure):
 class qr_params(ctypes.Structure):
     _fields_ = [("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("T_eps", ctypes.c_float), ("dilation", ctypes.c_float),
-                ("guard", ctypes.c_float)]
+                ("guard", ctypes.c_float), ("out_dtype", ctypes.c_int32)]
 
 
 def _load():
@@ -181,8 +181,9 @@ def make_camera(cam) -> qr_camera:
     return c
 
 
-def make_params(alpha_min=1.0 / 255.0, alpha_max=0.99, T_eps=1e-4, dilation=0.3, guard=1.3) -> qr_params:
-    return qr_params(alpha_min, alpha_max, T_eps, dilation, guard)
+def make_params(alpha_min=1.0 / 255.0, alpha_max=0.99, T_eps=1e-4, dilation=0.3, guard=1.3,
+                out_dtype=QR_F32) -> qr_params:
+    return qr_params(alpha_min, alpha_max, T_eps, dilation, guard, out_dtype)
 
 
 DTYPE_CODE = {torch.float32: QR_F32, torch.bfloat16: QR_BF16, torch.uint8: QR_FP8_E4M3}
@@ -321,7 +322,7 @@ def qr_render_quantile(width, height, params, K, tile_offsets, sorted_gid, means
                        sel_w=None, stream=None):
     fp, code, sp, dim = _feat_args(features, feature_scale)
     npx = _check_render(width, height, tile_offsets, sorted_gid, means2d, conic_opacity, features)
-    _need(out, npx * dim, F32, "out")
+    _need(out, npx * dim, (torch.bfloat16,) if params.out_dtype == QR_BF16 else F32, "out")
     _need(T_q, npx, F32, "T_q")
     _need(n_sel, npx, I32, "n_sel")
     _need(sel_gid, npx * K, I32, "sel_gid")

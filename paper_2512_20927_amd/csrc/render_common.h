@@ -98,7 +98,8 @@ __device__ __forceinline__ float4 load_feat4_global(const QR_GLOBAL void* __rest
   }
 }
 
-// Host-side validation shared by the render entry points.
+// Host-side validation shared by the render entry points (callers that write
+// float32 only also check prm->out_dtype == QR_F32 themselves).
 inline int validate_render(const char* name, int32_t width, int32_t height, const qr_params* prm,
                            const uint32_t* tile_offsets, const uint32_t* sorted_gid,
                            const float* means2d, const float* conic_opacity, const void* features,
@@ -111,6 +112,8 @@ inline int validate_render(const char* name, int32_t width, int32_t height, cons
   if (!(prm->alpha_min > 0.f) || !(prm->alpha_max >= prm->alpha_min) || !(prm->alpha_max < 1.f))
     return fail(QR_ERR_INVALID_ARG, "%s: need 0 < alpha_min <= alpha_max < 1", name);
   if (!(prm->T_eps >= 0.f)) return fail(QR_ERR_INVALID_ARG, "%s: T_eps must be >= 0", name);
+  if (prm->out_dtype != QR_F32 && prm->out_dtype != QR_BF16)
+    return fail(QR_ERR_UNSUPPORTED, "%s: unknown output dtype %d", name, prm->out_dtype);
   if (!tile_offsets || !sorted_gid || !means2d || !conic_opacity || !features || !out)
     return fail(QR_ERR_INVALID_ARG, "%s: null array pointer", name);
   if (dtype != QR_F32 && dtype != QR_BF16 && dtype != QR_FP8_E4M3)

@@ -200,6 +200,8 @@ extern "C" int qr_render_dense(void* stream, int32_t width, int32_t height, cons
   int rc = validate_render("qr_render_dense", width, height, prm, tile_offsets, sorted_gid,
                            means2d, conic_opacity, features, dtype, feature_scale, dim, out);
   if (rc != QR_OK) return rc;
+  if (prm->out_dtype != QR_F32)
+    return fail(QR_ERR_UNSUPPORTED, "qr_render_dense: float32 output only");
   const int tiles_x = static_cast<int>(ceil_div(width, kTile));
   const int tiles_y = static_cast<int>(ceil_div(height, kTile));
   const int n_tiles = tiles_x * tiles_y;

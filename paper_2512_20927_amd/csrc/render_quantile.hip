@@ -57,12 +57,29 @@ __device__ __forceinline__ void accum_rows(const GView& v, const int* ug, const 
   }
 }
 
+// Stores four features (columns 4 c4 .. 4 c4 + 3) of map pixel pix, as
+// float32 or as bfloat16 codes rounded to nearest even (OT = QR_BF16).
+template <int OT>
+__device__ __forceinline__ void store_out4(QR_GLOBAL float* out, int64_t pix, int dim, int c4,
+                                           float4 v) {
+  if constexpr (OT == QR_F32) {
+    store_stream(reinterpret_cast<QR_GLOBAL float4*>(out + pix * dim) + c4, v);
+  } else {
+    const u32x2 x = {static_cast<uint32_t>(__builtin_bit_cast(uint16_t, static_cast<__bf16>(v.x))) |
+                         (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, static_cast<__bf16>(v.y))) << 16),
+                     static_cast<uint32_t>(__builtin_bit_cast(uint16_t, static_cast<__bf16>(v.z))) |
+                         (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, static_cast<__bf16>(v.w))) << 16)};
+    __builtin_nontemporal_store(
+        x, reinterpret_cast<QR_GLOBAL u32x2*>(reinterpret_cast<QR_GLOBAL uint16_t*>(out) + pix * dim + 4 * c4));
+  }
+}
+
 // Gather-blend of one 4-pixel group whose distinct selections are merged:
 // out[p] = sum_e (w_pe / (1 - T^Q_p)) f_e (the normalisation is folded into
 // the merged weights). Each lane owns two float4 columns per pass (512
 // features per pass for the wave); rows are taken four at a time, the last
 // two or one on their own, so no multiply is spent on padding.
-template <int DT>
+template <int DT, int OT>
 __device__ __forceinline__ void gather_group_merged(const GView& v, const QuantileLds& L, int grp,
                                                     int nu, int tx, int ty, int lane, int dim) {
   const int dim4 = dim >> 2;
@@ -91,16 +108,16 @@ __device__ __forceinline__ void gather_group_merged(const GView& v, const Quanti
       const int p = p0 + q;
       if (L.ns[p] < 0) continue;  // outside the image
       const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
-      QR_GLOBAL float4* dst = reinterpret_cast<QR_GLOBAL float4*>(v.out + (static_cast<int64_t>(gy) * v.W + gx) * dim);
-      if (c0 < dim4) store_stream(dst + c0, a0[q]);
-      if (c1 < dim4) store_stream(dst + c1, a1[q]);
+      const int64_t pix = static_cast<int64_t>(gy) * v.W + gx;
+      if (c0 < dim4) store_out4<OT>(v.out, pix, dim, c0, a0[q]);
+      if (c1 < dim4) store_out4<OT>(v.out, pix, dim, c1, a1[q]);
     }
   }
 }
 
 // Gather-blend of a group with more than kUCap distinct selections: pixel
 // by pixel, each selection's row loaded for its own pixel.
-template <int DT>
+template <int DT, int OT>
 __device__ __forceinline__ void gather_group_per_pixel(const GView& v, const QuantileLds& L,
                                                        const int* __restrict__ s_sel_pos,
                                                        const float* __restrict__ s_sel_w, int KP,
@@ -144,9 +161,9 @@ __device__ __forceinline__ void gather_group_per_pixel(const GView& v, const Qua
       if (n[q] < 0) continue;  // outside the image
       const int p = p0 + q;
       const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
-      QR_GLOBAL float4* dst = reinterpret_cast<QR_GLOBAL float4*>(v.out + (static_cast<int64_t>(gy) * v.W + gx) * dim);
       const float inv = L.inv[p];
-      store_stream(dst + c, make_float4(acc[q].x * inv, acc[q].y * inv, acc[q].z * inv, acc[q].w * inv));
+      store_out4<OT>(v.out, static_cast<int64_t>(gy) * v.W + gx, dim, c,
+                     make_float4(acc[q].x * inv, acc[q].y * inv, acc[q].z * inv, acc[q].w * inv));
     }
   }
 }
@@ -158,7 +175,7 @@ __device__ __forceinline__ void gather_group_per_pixel(const GView& v, const Qua
 // gather groups it owns, so everything after the walk is wave-local.
 // Shared LDS (the record batch) is only rewritten after a barrier that every
 // wave reaches once it has finished the previous tile.
-template <int DT>
+template <int DT, int OT>
 __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, int dim,
                                               const qr_params& prm, QuantileLds& L,
                                               int* __restrict__ s_sel_gid,
@@ -190,9 +207,9 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
     const int grp = wave * kWaveGroups + gl;
     const int nu = __builtin_amdgcn_readfirstlane(L.unum[grp]);
     if (nu >= 0)
-      gather_group_merged<DT>(v, L, grp, nu, tx, ty, lane, dim);
+      gather_group_merged<DT, OT>(v, L, grp, nu, tx, ty, lane, dim);
     else  // more distinct selections than kUCap (rare)
-      gather_group_per_pixel<DT>(v, L, s_sel_pos, s_sel_w, KP, grp, tx, ty, lane, dim);
+      gather_group_per_pixel<DT, OT>(v, L, s_sel_pos, s_sel_w, KP, grp, tx, ty, lane, dim);
   }
   // Per-pixel outputs last: a load issued after a store waits for it, so no
   // store precedes the loads of the merge and the gather.
@@ -210,7 +227,7 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
   }
 }
 
-template <int DT>
+template <int DT, int OT>
 __global__ void __launch_bounds__(kTilePix, kWavesPerSimd)
 render_quantile_kernel(ViewArgs v, int n_tiles, qr_params prm, int K, int dim,
                        int32_t* __restrict__ sel_gid_out, float* __restrict__ sel_w_out) {
@@ -218,7 +235,7 @@ render_quantile_kernel(ViewArgs v, int n_tiles, qr_params prm, int K, int dim,
   __shared__ QuantileLds L;
   int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);                            // [256][KP]
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);  // [256][KP]
-  quantile_tile<DT>(to_global(v), xcd_remap(blockIdx.x, n_tiles), K, dim, prm, L, s_sel_gid,
+  quantile_tile<DT, OT>(to_global(v), xcd_remap(blockIdx.x, n_tiles), K, dim, prm, L, s_sel_gid,
                     s_sel_w, sel_gid_out, sel_w_out);
 }
 
@@ -234,7 +251,7 @@ __device__ __forceinline__ uint32_t queue_begin(int64_t n_items, int q) {
   return static_cast<uint32_t>(n_items * q / kXcdQueues);
 }
 
-template <int DT>
+template <int DT, int OT>
 __global__ void __launch_bounds__(kTilePix, kWavesPerSimd)
 render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t* __restrict__ schedule,
                                int64_t n_items, uint32_t* __restrict__ counter, qr_params prm,
@@ -269,7 +286,7 @@ render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t
     if (item >= n_items) break;
     const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[item]);
     const GView v = to_global(view_args(views[packed >> kViewShift]));
-    quantile_tile<DT>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
+    quantile_tile<DT, OT>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
                       nullptr, nullptr);
   }
 }
@@ -278,7 +295,7 @@ render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t
 // dealt to the XCDs in contiguous runs of the schedule (neighbouring tiles of
 // a view share L2 contents); workgroups retire as they finish, so work on
 // other streams can take their slots.
-template <int DT>
+template <int DT, int OT>
 __global__ void __launch_bounds__(kTilePix, kWavesPerSimd)
 render_quantile_batched_grid_kernel(const qr_view* __restrict__ views,
                                     const uint32_t* __restrict__ schedule, int n_items,
@@ -289,7 +306,7 @@ render_quantile_batched_grid_kernel(const qr_view* __restrict__ views,
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);
   const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[xcd_remap(blockIdx.x, n_items)]);
   const GView v = to_global(view_args(views[packed >> kViewShift]));
-  quantile_tile<DT>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
+  quantile_tile<DT, OT>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
                     nullptr, nullptr);
 }
 
@@ -300,6 +317,24 @@ __global__ void reset_counter_kernel(uint32_t* __restrict__ c) {
 }  // namespace qr
 
 using namespace qr;
+
+// Instantiates QR_LAUNCH(feature dtype, output dtype) for the runtime pair.
+#define QR_DISPATCH(dt, ot)                                  \
+  do {                                                       \
+    if ((ot) == QR_BF16) {                                   \
+      switch (dt) {                                          \
+        case QR_F32: QR_LAUNCH(QR_F32, QR_BF16); break;      \
+        case QR_BF16: QR_LAUNCH(QR_BF16, QR_BF16); break;    \
+        default: QR_LAUNCH(QR_FP8_E4M3, QR_BF16); break;     \
+      }                                                      \
+    } else {                                                 \
+      switch (dt) {                                          \
+        case QR_F32: QR_LAUNCH(QR_F32, QR_F32); break;       \
+        case QR_BF16: QR_LAUNCH(QR_BF16, QR_F32); break;     \
+        default: QR_LAUNCH(QR_FP8_E4M3, QR_F32); break;      \
+      }                                                      \
+    }                                                        \
+  } while (0)
 
 extern "C" int qr_render_quantile(void* stream, int32_t width, int32_t height,
                                   const qr_params* prm, int32_t K, const uint32_t* tile_offsets,
@@ -323,14 +358,10 @@ extern "C" int qr_render_quantile(void* stream, int32_t width, int32_t height,
   const ViewArgs v{width, height, tile_offsets, sorted_gid, reinterpret_cast<const float2*>(means2d),
                    reinterpret_cast<const float4*>(conic_opacity), features, feature_scale, out, T_q,
                    n_sel};
-#define QR_LAUNCH(DT)                                                                              \
-  hipLaunchKernelGGL(render_quantile_kernel<DT>, dim3(n_tiles), dim3(kTilePix), lds, s, v, n_tiles, \
-                     *prm, K, dim, sel_gid, sel_w)
-  switch (dtype) {
-    case QR_F32: QR_LAUNCH(QR_F32); break;
-    case QR_BF16: QR_LAUNCH(QR_BF16); break;
-    default: QR_LAUNCH(QR_FP8_E4M3); break;
-  }
+#define QR_LAUNCH(DT, OT)                                                                          \
+  hipLaunchKernelGGL((render_quantile_kernel<DT, OT>), dim3(n_tiles), dim3(kTilePix), lds, s, v,    \
+                     n_tiles, *prm, K, dim, sel_gid, sel_w)
+  QR_DISPATCH(dtype, prm->out_dtype);
 #undef QR_LAUNCH
   return check_launch("qr_render_quantile");
 }
@@ -358,32 +389,26 @@ extern "C" int qr_render_quantile_batched(void* stream, int32_t n_views, const q
     return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile_batched: dim = %d", dim);
   if (!(prm->alpha_min > 0.f) || !(prm->alpha_max >= prm->alpha_min) || !(prm->alpha_max < 1.f))
     return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: need 0 < alpha_min <= alpha_max < 1");
+  if (prm->out_dtype != QR_F32 && prm->out_dtype != QR_BF16)
+    return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile_batched: unknown output dtype %d", prm->out_dtype);
   if (n_items == 0) return QR_OK;
   hipStream_t s = as_stream(stream);
   const size_t lds = static_cast<size_t>(kTilePix) * ((K + 3) & ~3) * (sizeof(int) + sizeof(float));
   if (n_workgroups == 0) {
     const int ni = static_cast<int>(n_items);
-#define QR_LAUNCH(DT)                                                                            \
-  hipLaunchKernelGGL(render_quantile_batched_grid_kernel<DT>, dim3(ni), dim3(kTilePix), lds, s, \
-                     views, schedule, ni, *prm, K, dim)
-    switch (dtype) {
-      case QR_F32: QR_LAUNCH(QR_F32); break;
-      case QR_BF16: QR_LAUNCH(QR_BF16); break;
-      default: QR_LAUNCH(QR_FP8_E4M3); break;
-    }
+#define QR_LAUNCH(DT, OT)                                                                          \
+  hipLaunchKernelGGL((render_quantile_batched_grid_kernel<DT, OT>), dim3(ni), dim3(kTilePix), lds, \
+                     s, views, schedule, ni, *prm, K, dim)
+    QR_DISPATCH(dtype, prm->out_dtype);
 #undef QR_LAUNCH
     return check_launch("qr_render_quantile_batched");
   }
   auto* counter = static_cast<uint32_t*>(workspace);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
-#define QR_LAUNCH(DT)                                                                             \
-  hipLaunchKernelGGL(render_quantile_batched_kernel<DT>, dim3(n_workgroups), dim3(kTilePix), lds, \
-                     s, views, schedule, n_items, counter, *prm, K, dim)
-  switch (dtype) {
-    case QR_F32: QR_LAUNCH(QR_F32); break;
-    case QR_BF16: QR_LAUNCH(QR_BF16); break;
-    default: QR_LAUNCH(QR_FP8_E4M3); break;
-  }
+#define QR_LAUNCH(DT, OT)                                                                          \
+  hipLaunchKernelGGL((render_quantile_batched_kernel<DT, OT>), dim3(n_workgroups), dim3(kTilePix),  \
+                     lds, s, views, schedule, n_items, counter, *prm, K, dim)
+  QR_DISPATCH(dtype, prm->out_dtype);
 #undef QR_LAUNCH
   return check_launch("qr_render_quantile_batched");
 }

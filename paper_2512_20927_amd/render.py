@@ -24,9 +24,11 @@ class RenderParams:
     T_eps: float = 1e-4
     dilation: float = 0.3
     guard: float = 1.3
+    out_dtype: int = L.QR_F32  # Q-Render feature maps: L.QR_F32 or L.QR_BF16
 
     def c(self) -> L.qr_params:
-        return L.make_params(self.alpha_min, self.alpha_max, self.T_eps, self.dilation, self.guard)
+        return L.make_params(self.alpha_min, self.alpha_max, self.T_eps, self.dilation, self.guard,
+                             self.out_dtype)
 
 
 def tiles_of(width: int, height: int):
@@ -167,7 +169,8 @@ def render_quantile(pr: Projected, bins: Bins, features, width: int, height: int
     dev = features.device
     dim = features.shape[1]
     if out is None:
-        out = torch.empty(height, width, dim, dtype=torch.float32, device=dev)
+        out_t = torch.bfloat16 if params.out_dtype == L.QR_BF16 else torch.float32
+        out = torch.empty(height, width, dim, dtype=out_t, device=dev)
     T_q = torch.empty(height, width, dtype=torch.float32, device=dev)
     n_sel = torch.empty(height, width, dtype=torch.int32, device=dev)
     sel_gid = sel_w = None

@@ -105,6 +105,16 @@ def test_render_validation(L):
     assert rc == L.QR_ERR_UNSUPPORTED
     rc = lib.qr_render_quantile_backward(None, 64, 64, P, 40, d, d, d, d, d, 0, None, 16, d, d, d, d)
     assert rc == L.QR_ERR_UNSUPPORTED
+    # output dtype: bf16 maps from Q-Render only; unknown codes rejected
+    bad_out = L.make_params(out_dtype=7)
+    rc = lib.qr_render_quantile(None, 64, 64, ctypes.byref(bad_out), 8, d, d, d, d, d, 0, None, 16, d,
+                                None, None, None, None)
+    assert rc == L.QR_ERR_UNSUPPORTED and "output dtype" in L.last_error()
+    bf_out = L.make_params(out_dtype=L.QR_BF16)
+    rc = lib.qr_render_dense(None, 64, 64, ctypes.byref(bf_out), d, d, d, d, d, 0, None, 16, d, None, None)
+    assert rc == L.QR_ERR_UNSUPPORTED and "float32 output" in L.last_error()
+    rc = lib.qr_render_quantile_batched(None, 1, d, ctypes.byref(bad_out), 8, 0, 16, d, 10, 0, None, 0)
+    assert rc == L.QR_ERR_UNSUPPORTED
     rc = lib.qr_quantize_features(None, 10, 16, d, 0, d, None)
     assert rc == L.QR_ERR_UNSUPPORTED
     rc = lib.qr_quantize_features(None, 10, 16, d, 2, d, None)
