@@ -71,7 +71,7 @@ class FrameRunner:
         n = scene_t["means"].shape[0]
         self.pr = qr.render.alloc_projected(n)
         self.binner = qr.Binner(n, self.W, self.H, capacity)
-        self.prm = qr.RenderParams().c()
+        self.prm = qr.RenderParams(out_dtype=L.QR_F32 if out_dtype is None else out_dtype).c()
         dev = "cuda"
         self.out = torch.empty(self.H, self.W, dim, dtype=torch.float32, device=dev)
         self.aux_f = torch.empty(self.H, self.W, dtype=torch.float32, device=dev)
@@ -128,14 +128,14 @@ class BatchState:
     the batched Q-Render launch over all (pose, tile) items."""
 
     def __init__(self, qr, L, scene_t, cams, W, H, capacity, outs, aux_f, aux_i, K, dim,
-                 dtype_code=None, scale=None):
+                 dtype_code=None, scale=None, out_dtype=None):
         import torch
         n = scene_t["means"].shape[0]
         self.L, self.s, self.W, self.H, self.dim = L, scene_t, W, H, dim
         self.dtype_code = L.QR_F32 if dtype_code is None else dtype_code
         self.scale = scale
         self.cams_c = L.make_cameras(cams)
-        self.prm = qr.RenderParams().c()
+        self.prm = qr.RenderParams(out_dtype=L.QR_F32 if out_dtype is None else out_dtype).c()
         self.pv = qr.render.alloc_projected(len(cams) * n)
         self.vb = qr.ViewsBinner(len(cams), n, W, H, capacity)
         self.outs, self.aux_f, self.aux_i = outs, aux_f, aux_i
@@ -376,9 +376,34 @@ def run_room(args):
     # bracket the batched launch alone (in the overlapped run the front of the
     # next step shares the GPU with it)
     achieved = bytes_batch / (k_seq * 1e-3) / 1e9
-    kernel = ("render_quantile_batched_grid_kernel<0>" if tuned["wg_per_cu"] == 0
-              else "render_quantile_batched_kernel<0>")
+    kernel = ("render_quantile_batched_grid_kernel<0, 0>" if tuned["wg_per_cu"] == 0
+              else "render_quantile_batched_kernel<0, 0>")
     traffic = measured_traffic(kernel, "room")
+
+    # side result: the same steps writing bfloat16 maps (half the output
+    # bytes; the map is the float32 result rounded at the store)
+    bf16_side = None
+    if not args.renders_only:
+        outs_bf = [torch.empty(H, W, D, dtype=torch.bfloat16, device="cuda") for _ in range(n_views)]
+        states_bf = [BatchState(qr, L, s, cams, W, H, capacity, outs_bf, aux_f, aux_i, K, D,
+                                out_dtype=L.QR_BF16) for _ in range(2)]
+        for st in states_bf:
+            st.front()
+        tuned_bf, _ = autotune(states_bf[0].bq, wg_per_cu=(0, 3, 8), use_cache=False)
+        dtb_seq, kb_seq = timed_batched(states_bf, args.steps, args.warmup, tuned_bf["schedule"],
+                                        tuned_bf["wg_per_cu"], overlap=False)
+        dtb_ovl, _ = timed_batched(states_bf, args.steps, args.warmup, tuned_bf["schedule"],
+                                   tuned_bf["wg_per_cu"], overlap=True)
+        bytes_bf = float(np.sum([n_px * (D * 2 + 8) + p * 28 + (n_tiles + 1) * 8 + u * D * 4
+                                 for p, u in zip(pairs, uniq)]))
+        ach_bf = bytes_bf / (kb_seq * 1e-3) / 1e9
+        bf16_side = {"value": round(frames / min(dtb_seq, dtb_ovl), 2), "unit": "frames/s",
+                     "render_ms": round(kb_seq, 4),
+                     "batched_launch": {k: tuned_bf[k] for k in ("schedule", "wg_per_cu")},
+                     "roofline": {"bound": "hbm", "achieved": round(ach_bf, 1), "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(ach_bf / HBM_PEAK_GBS, 4),
+                                  "bytes_per_launch": round(bytes_bf)}}
+        del states_bf, outs_bf
 
     cpu = None
     if args.cpu_budget > 0 and not args.renders_only:
@@ -420,6 +445,7 @@ def run_room(args):
                      "traffic": traffic,
                      "bytes_per_launch": round(bytes_batch), "frames_per_launch": n_views},
         "cpu_baseline": cpu,
+        "bf16_output": bf16_side,
         "autotune_ms": {k: round(v, 3) for k, v in tune_ms.items()},
         "setup_s": round(t_setup, 1),
     }
