@@ -355,6 +355,28 @@ int qr_render_quantile_backward(void* stream, int32_t width, int32_t height,
                                 float* grad_means2d, float* grad_conic_opacity);
 
 /*
+ * qr_autotune_batched - the launch-shape autotuner of
+ * qr_render_quantile_batched: for every candidate (schedule i of the host
+ * array `schedules` of n_sched device schedules, each u32[n_items]; j of the
+ * host array wg_per_cu[n_wg], 0 = one workgroup per item, w > 0 = w
+ * persistent workgroups per CU of the current device), one warm-up launch and
+ * `reps` timed launches on `stream` (HIP events; the call synchronises on
+ * them). Writes the mean launch time to timings_ms[i * n_wg + j] (host) and
+ * the fastest candidate to *best_schedule, *best_wg_per_cu (host). The
+ * rendered outputs are those of the last launch. Other arguments as for
+ * qr_render_quantile_batched; workspace >= 32 bytes if any w > 0.
+ * Errors: QR_ERR_INVALID_ARG for null host pointers, counts < 1 or w outside
+ * [0, 64]; any error of qr_render_quantile_batched; QR_ERR_HIP for event
+ * failures.
+ */
+int qr_autotune_batched(void* stream, int32_t n_views, const qr_view* views,
+                        const qr_params* prm, int32_t K, int32_t dtype, int32_t dim,
+                        const uint32_t* const* schedules, int32_t n_sched, int64_t n_items,
+                        const int32_t* wg_per_cu, int32_t n_wg, int32_t reps, void* workspace,
+                        size_t workspace_bytes, float* timings_ms, int32_t* best_schedule,
+                        int32_t* best_wg_per_cu);
+
+/*
  * qr_render_quantile_batched_backward - qr_render_quantile_backward for many
  * views in one launch over the (view, tile) items of `schedule`, the same
  * schedule format and launch modes as qr_render_quantile_batched (n_workgroups

@@ -29,7 +29,7 @@ EXPORTED = [
     "qr_bin_sort_workspace_size", "qr_bin_sort", "qr_render_dense", "qr_render_quantile",
     "qr_render_dense_backward", "qr_render_quantile_backward", "qr_quantize_features",
     "qr_render_quantile_batched", "qr_batch_schedule", "qr_project_views", "qr_bin_sort_views",
-    "qr_render_quantile_batched_backward",
+    "qr_render_quantile_batched_backward", "qr_autotune_batched",
 ]
 QR_BATCH_TILE_BITS = 20
 
@@ -92,6 +92,9 @@ def _load():
         "qr_render_quantile_batched": ([P, i32, P, prm_p, i32, i32, i32, P, i64, i32, P, sz], i32),
         "qr_batch_schedule": ([P, i32, P, P, i64, P, P, sz], i32),
         "qr_render_quantile_batched_backward": ([P, i32, P, P, prm_p, i32, i32, i32, P, i64, i32, P, sz], i32),
+        "qr_autotune_batched": ([P, i32, P, prm_p, i32, i32, i32, ctypes.POINTER(ctypes.c_void_p), i32, i64,
+                                 ctypes.POINTER(i32), i32, i32, P, sz, ctypes.POINTER(ctypes.c_float),
+                                 ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -411,6 +414,32 @@ def qr_render_quantile_batched_backward(n_views, views_dev, grads_dev, params, K
         _stream(stream), n_views, _ptr(views_dev), _ptr(grads_dev), ctypes.byref(params), K,
         dtype_code, dim, _ptr(schedule), schedule.numel(), n_workgroups,
         _ptr(workspace) if workspace is not None else None, ws_bytes))
+
+
+def qr_autotune_batched(n_views, views_dev, params, K, dtype_code, dim, schedules, wg_per_cu, reps,
+                        workspace, stream=None):
+    """Times qr_render_quantile_batched for every (schedule, workgroups per
+    CU) pair; schedules: int32 device tensors of n_items packed items each.
+    Returns (best schedule index, best workgroups per CU, timings_ms as a
+    [len(schedules)][len(wg_per_cu)] list)."""
+    if views_dev.numel() < n_views * ctypes.sizeof(qr_view):
+        raise ValueError("views_dev is smaller than n_views qr_view records")
+    n_items = schedules[0].numel()
+    for sch in schedules:
+        _need(sch, n_items, I32, "schedule")
+        if sch.numel() != n_items:
+            raise ValueError("schedules differ in length")
+    ns, nw = len(schedules), len(wg_per_cu)
+    sch_ptrs = (ctypes.c_void_p * ns)(*[sch.data_ptr() for sch in schedules])
+    wg = (ctypes.c_int32 * nw)(*wg_per_cu)
+    times = (ctypes.c_float * (ns * nw))()
+    bi, bw = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(_LIB.qr_autotune_batched(_stream(stream), n_views, _ptr(views_dev), ctypes.byref(params), K,
+                                    dtype_code, dim, sch_ptrs, ns, n_items, wg, nw, reps,
+                                    _ptr(workspace) if workspace is not None else None, ws_bytes,
+                                    times, ctypes.byref(bi), ctypes.byref(bw)))
+    return bi.value, bw.value, [[times[i * nw + j] for j in range(nw)] for i in range(ns)]
 
 
 def pack_grads(grads) -> bytes:

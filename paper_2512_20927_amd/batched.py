@@ -115,8 +115,8 @@ def default_cache_path() -> str:
 def autotune(bq: BatchedQuantile, wg_per_cu=(0, 2, 4, 8), schedules=SCHEDULES, reps: int = 3,
              cache_path: str | None = None, use_cache: bool = True):
     """Times every (schedule, workgroups per CU) candidate (0 workgroups per
-    CU = one workgroup per item) and returns (best_config, timings_ms). The
-    best is cached under bq.key()."""
+    CU = one workgroup per item) through qr_autotune_batched and returns
+    (best_config, timings_ms). The best is cached under bq.key()."""
     cache_path = cache_path or default_cache_path()
     cache = {}
     if use_cache and os.path.exists(cache_path):
@@ -127,21 +127,14 @@ def autotune(bq: BatchedQuantile, wg_per_cu=(0, 2, 4, 8), schedules=SCHEDULES, r
             cache = {}
         if bq.key() in cache:
             return cache[bq.key()], {}
-    timings = {}
-    for kind in schedules:
-        for w in wg_per_cu:
-            bq.render(kind, w)  # warm
-            torch.cuda.synchronize()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(reps):
-                bq.render(kind, w)
-            b.record()
-            torch.cuda.synchronize()
-            timings["%s/%d" % (kind, w)] = a.elapsed_time(b) / reps
-    best = min(timings, key=timings.get)
-    kind, w = best.split("/")
-    cfg = {"schedule": kind, "wg_per_cu": int(w), "ms": timings[best]}
+    # the timing loop runs in the library (qr_autotune_batched, HIP events)
+    scheds = [bq.schedule(kind) for kind in schedules]  # builds the device-side schedules
+    bi, bw, ms = L.qr_autotune_batched(bq.n_views, bq.views_dev, bq.params, bq.K, bq.dtype_code,
+                                       bq.dim, scheds, list(wg_per_cu), reps, bq.counter)
+    timings = {"%s/%d" % (kind, w): ms[i][j] for i, kind in enumerate(schedules)
+               for j, w in enumerate(wg_per_cu)}
+    kind, w = schedules[bi], bw
+    cfg = {"schedule": kind, "wg_per_cu": int(w), "ms": timings["%s/%d" % (kind, w)]}
     cache[bq.key()] = cfg
     try:
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)

@@ -29,6 +29,7 @@ SOURCES = [
     "render_quantile_backward.hip",
     "quantize.hip",
     "schedule.hip",
+    "autotune.hip",
 ]
 
 # Packed FP32 instructions are switched off: float code is compiled to

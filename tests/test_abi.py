@@ -156,6 +156,21 @@ def test_batched_validation(L):
     assert bb(1, 0, 0, None, 0) == L.QR_OK
     rc = lib.qr_batch_schedule(None, 0, d, d, 10, d, d, 256)
     assert rc == L.QR_ERR_INVALID_ARG
+    # autotuner: host-side argument checks before any launch
+    sch = (ctypes.c_void_p * 2)(0x1000, 0x1000)
+    wg = (ctypes.c_int32 * 2)(0, 3)
+    times = (ctypes.c_float * 4)()
+    bi, bw = ctypes.c_int32(), ctypes.c_int32()
+
+    def at(n_sched=2, n_wg=2, reps=2, schedules=sch, wgs=wg, t=times):
+        return lib.qr_autotune_batched(None, 1, d, P, 8, 0, 16, schedules, n_sched, 10, wgs, n_wg, reps,
+                                       d, 64, t, ctypes.byref(bi), ctypes.byref(bw))
+
+    assert at(reps=0) == L.QR_ERR_INVALID_ARG
+    assert at(n_sched=0) == L.QR_ERR_INVALID_ARG
+    assert at(t=None) == L.QR_ERR_INVALID_ARG
+    assert at(schedules=(ctypes.c_void_p * 2)(0x1000, None)) == L.QR_ERR_INVALID_ARG
+    assert at(wgs=(ctypes.c_int32 * 2)(0, 65)) == L.QR_ERR_INVALID_ARG
     rc = lib.qr_batch_schedule(None, 2, d, d, 10, d, d, 16)
     assert rc == L.QR_ERR_CAPACITY
 

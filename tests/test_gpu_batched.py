@@ -99,6 +99,7 @@ def test_autotuner_picks_a_candidate_and_caches(qr, tmp_path):
     path = str(tmp_path / "tune.json")
     cfg, timings = autotune(bq, wg_per_cu=(0, 4), reps=2, cache_path=path)
     assert cfg["schedule"] in ("natural", "heavy") and cfg["wg_per_cu"] in (0, 4)
-    assert len(timings) == 4
+    assert len(timings) == 4 and all(t > 0 for t in timings.values())
+    assert cfg["ms"] == min(timings.values())  # the library's choice is the fastest candidate
     cfg2, timings2 = autotune(bq, cache_path=path)
     assert cfg2 == cfg and timings2 == {}
