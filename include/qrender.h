@@ -64,6 +64,12 @@ typedef enum qr_dtype {
   QR_FP8_E4M3 = 2  /* OCP FP8 e4m3 code times a per-Gaussian float32 scale */
 } qr_dtype;
 
+/* Threshold rules of the Q-Render selection (qr_params.selection). */
+typedef enum {
+  QR_SELECT_QUANTILE = 0,   /* Algorithm 1 */
+  QR_SELECT_STRATIFIED = 1  /* Stratified-K (Appendix) */
+} qr_selection;
+
 /* Pinhole camera, OpenCV axes (x right, y down, z forward). A world point X
  * maps to camera space as R_cw X + t (R_cw row-major). Gaussians whose
  * camera-space depth is <= z_near are culled. */
@@ -98,6 +104,16 @@ typedef struct qr_params {
    * float32 only (QR_ERR_UNSUPPORTED otherwise); the backward passes ignore
    * it. */
   int32_t out_dtype;
+  /* Thresholds of the Q-Render selection: QR_SELECT_QUANTILE (0, default,
+   * Algorithm 1: t_m = 1 - m/(K+1)) or QR_SELECT_STRATIFIED (1, the
+   * Stratified-K variant of the Appendix: per ray, a first pass estimates the
+   * mean mu and population standard deviation sigma of T_0 = 1 and the
+   * transmittance after every Gaussian the dense blend composites (with its
+   * T_eps stop); then t_m = clip(mu + sigma Phi^-1(1 - m/(K+1)), 0, 1),
+   * evaluated in double and rounded once to float, and Algorithm 1 runs with
+   * these thresholds, ending once all K are consumed). The backward passes
+   * support QR_SELECT_QUANTILE only. */
+  int32_t selection;
 } qr_params;
 
 /* One view of a batched render (qr_render_quantile_batched). All pointers are

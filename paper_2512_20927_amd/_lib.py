@@ -21,6 +21,7 @@ LIB_PATH = os.environ.get("QRENDER_LIB") or os.path.join(
 
 QR_OK, QR_ERR_INVALID_ARG, QR_ERR_UNSUPPORTED, QR_ERR_CAPACITY, QR_ERR_HIP = 0, -1, -2, -3, -4
 QR_F32, QR_BF16, QR_FP8_E4M3 = 0, 1, 2
+QR_SELECT_QUANTILE, QR_SELECT_STRATIFIED = 0, 1
 QR_TILE = 16
 QR_MAX_K = 32
 
@@ -64,7 +65,7 @@ class qr_view_grad(ctypes.Structure):
 class qr_params(ctypes.Structure):
     _fields_ = [("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("T_eps", ctypes.c_float), ("dilation", ctypes.c_float),
-                ("guard", ctypes.c_float), ("out_dtype", ctypes.c_int32)]
+                ("guard", ctypes.c_float), ("out_dtype", ctypes.c_int32), ("selection", ctypes.c_int32)]
 
 
 def _load():
@@ -185,8 +186,8 @@ def make_camera(cam) -> qr_camera:
 
 
 def make_params(alpha_min=1.0 / 255.0, alpha_max=0.99, T_eps=1e-4, dilation=0.3, guard=1.3,
-                out_dtype=QR_F32) -> qr_params:
-    return qr_params(alpha_min, alpha_max, T_eps, dilation, guard, out_dtype)
+                out_dtype=QR_F32, selection=0) -> qr_params:
+    return qr_params(alpha_min, alpha_max, T_eps, dilation, guard, out_dtype, selection)
 
 
 DTYPE_CODE = {torch.float32: QR_F32, torch.bfloat16: QR_BF16, torch.uint8: QR_FP8_E4M3}

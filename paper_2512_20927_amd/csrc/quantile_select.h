@@ -111,22 +111,69 @@ struct PixelSel {
 // 1 / (1 - T^Q). Workgroup barriers occur only around the staging of record
 // batches; the record batch is only rewritten after a barrier that every
 // wave reaches once it has finished the previous tile.
-template <class WalkLds>
+// MODE QR_SELECT_QUANTILE: Algorithm 1's thresholds t_m = 1 - m/(K+1).
+// MODE QR_SELECT_STRATIFIED (Stratified-K, Appendix): a first pass over the
+// list estimates the mean and spread of the ray's transmittance values (T_0 =
+// 1 and T after every Gaussian the dense blend composites, with its T_eps
+// stop; sums in double) and the thresholds are the ray's own.
+template <int MODE, class WalkLds>
 __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi, int K, float pxc,
                                                   float pyc, bool inside, const qr_params& prm,
                                                   WalkLds& L, int* __restrict__ s_sel_pos,
                                                   float* __restrict__ s_sel_w, int KP) {
   const int tid = threadIdx.x;
   // thr[k] = t_{k+1}; thr[K] = 0 (identical for every tile of a launch)
-  if (tid <= K) L.thr[tid] = quantile_threshold(tid + 1, K);
+  if (MODE == QR_SELECT_QUANTILE && tid <= K) L.thr[tid] = quantile_threshold(tid + 1, K);
+  const float amin = prm.alpha_min, amax = prm.alpha_max;
+
+  double mu = 0.0, sigma = 0.0;
+  if constexpr (MODE == QR_SELECT_STRATIFIED) {
+    double s1 = 1.0, s2 = 1.0;  // T_0 = 1
+    int n = 1;
+    float T1 = 1.f;
+    bool stop = !inside;
+    for (int batch = lo; batch < hi; batch += kTilePix) {
+      if (__syncthreads_count(!stop) == 0) break;
+      const int idx = batch + tid;
+      if (idx < hi) {
+        const int g = static_cast<int>(v.sorted_gid[idx]);
+        const f32x2 m = v.means2d[g];
+        const f32x4 c = v.conic_opacity[g];
+        L.mean[tid] = make_float2(m.x, m.y);
+        L.co[tid] = make_float4(c.x, c.y, c.z, c.w);
+      }
+      __syncthreads();
+      const int cnt = min(kTilePix, hi - batch);
+      for (int j = 0; j < cnt && !stop; ++j) {
+        const float alpha = gauss_alpha(L.mean[j], L.co[j], pxc, pyc, amax);
+        if (alpha < amin) continue;
+        const float T_test = T1 * (1.f - alpha);
+        if (T_test < prm.T_eps) {
+          stop = true;
+        } else {
+          T1 = T_test;
+          s1 += T1;
+          s2 += static_cast<double>(T1) * T1;
+          ++n;
+        }
+      }
+    }
+    mu = s1 / n;
+    sigma = sqrt(fmax(s2 / n - mu * mu, 0.0));
+  }
+  auto threshold = [&](int kk) -> float {  // t_{kk+1}
+    if constexpr (MODE == QR_SELECT_STRATIFIED) return stratified_threshold(kk + 1, K, mu, sigma);
+    else return L.thr[kk];
+  };
 
   float T = 1.f, TQ = 1.f;
   int k = 0, ns = 0;
   bool done = !inside;
-  float thr_k = quantile_threshold(1, K);  // t_{k+1}: changes only at a crossing
+  // t_{k+1}: changes only at a crossing
+  float thr_k = MODE == QR_SELECT_STRATIFIED ? stratified_threshold(1, K, mu, sigma)
+                                             : quantile_threshold(1, K);
   int* my_pos = s_sel_pos + tid * KP;
   float* my_w = s_sel_w + tid * KP;
-  const float amin = prm.alpha_min, amax = prm.alpha_max;
 
   for (int batch = lo; batch < hi; batch += kTilePix) {
     if (__syncthreads_count(!done) == 0) break;
@@ -166,8 +213,8 @@ __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi
           ++ns;
           TQ = TQ * (1.f - alpha);
           ++k;
-          while (k < K && T_test < L.thr[k]) ++k;  // thresholds crossed by the same step
-          thr_k = L.thr[k];
+          while (k < K && T_test < threshold(k)) ++k;  // thresholds crossed by the same step
+          thr_k = threshold(k);
           if (k == K) done = true;
         }
         T = T_test;
@@ -249,12 +296,13 @@ __device__ __forceinline__ void merge_groups(const GView& v, QuantileLds& L,
 }
 
 // Walk and merge (the forward renderer's selection phase).
+template <int MODE>
 __device__ __forceinline__ PixelSel quantile_select(const GView& v, int lo, int hi, int K,
                                                     float pxc, float pyc, bool inside,
                                                     const qr_params& prm, QuantileLds& L,
                                                     int* __restrict__ s_sel_pos,
                                                     float* __restrict__ s_sel_w, int KP) {
-  const PixelSel sel = quantile_walk(v, lo, hi, K, pxc, pyc, inside, prm, L, s_sel_pos, s_sel_w, KP);
+  const PixelSel sel = quantile_walk<MODE>(v, lo, hi, K, pxc, pyc, inside, prm, L, s_sel_pos, s_sel_w, KP);
   merge_groups(v, L, s_sel_pos, s_sel_w, KP);
   return sel;
 }

@@ -26,6 +26,15 @@ __device__ __forceinline__ float quantile_threshold(int m, int K) {
   return static_cast<float>(1.0 - static_cast<double>(m) / static_cast<double>(K + 1));
 }
 
+// Stratified-K threshold t_m = clip(mu + sigma Phi^-1(1 - m/(K+1)), 0, 1) in
+// double, rounded once to float; m = K+1 gives -1, which no transmittance
+// crosses.
+__device__ __forceinline__ float stratified_threshold(int m, int K, double mu, double sigma) {
+  if (m > K) return -1.f;
+  const double t = mu + sigma * normcdfinv(1.0 - static_cast<double>(m) / static_cast<double>(K + 1));
+  return static_cast<float>(fmin(fmax(t, 0.0), 1.0));
+}
+
 // alpha' = min(alpha_max, o exp(power)), power = -(a dx^2 + 2 b dx dy + c dy^2)/2,
 // with every multiply-add written out so that forward and backward kernels
 // evaluate bit-identical values.
@@ -114,6 +123,8 @@ inline int validate_render(const char* name, int32_t width, int32_t height, cons
   if (!(prm->T_eps >= 0.f)) return fail(QR_ERR_INVALID_ARG, "%s: T_eps must be >= 0", name);
   if (prm->out_dtype != QR_F32 && prm->out_dtype != QR_BF16)
     return fail(QR_ERR_UNSUPPORTED, "%s: unknown output dtype %d", name, prm->out_dtype);
+  if (prm->selection != QR_SELECT_QUANTILE && prm->selection != QR_SELECT_STRATIFIED)
+    return fail(QR_ERR_UNSUPPORTED, "%s: unknown selection rule %d", name, prm->selection);
   if (!tile_offsets || !sorted_gid || !means2d || !conic_opacity || !features || !out)
     return fail(QR_ERR_INVALID_ARG, "%s: null array pointer", name);
   if (dtype != QR_F32 && dtype != QR_BF16 && dtype != QR_FP8_E4M3)

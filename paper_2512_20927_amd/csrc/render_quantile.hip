@@ -175,7 +175,7 @@ __device__ __forceinline__ void gather_group_per_pixel(const GView& v, const Qua
 // gather groups it owns, so everything after the walk is wave-local.
 // Shared LDS (the record batch) is only rewritten after a barrier that every
 // wave reaches once it has finished the previous tile.
-template <int DT, int OT>
+template <int DT, int OT, int MODE>
 __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, int dim,
                                               const qr_params& prm, QuantileLds& L,
                                               int* __restrict__ s_sel_gid,
@@ -195,7 +195,7 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
   const int hi = static_cast<int>(v.tile_offsets[tile + 1]);
   const int KP = (K + 3) & ~3;  // selection row stride: 16-byte aligned rows
   int* s_sel_pos = s_sel_gid;   // selections are kept as tile-list positions
-  const PixelSel sel = quantile_select(v, lo, hi, K, pxc, pyc, inside, prm, L, s_sel_pos, s_sel_w, KP);
+  const PixelSel sel = quantile_select<MODE>(v, lo, hi, K, pxc, pyc, inside, prm, L, s_sel_pos, s_sel_w, KP);
   const int ns = sel.ns;
   const float TQ = sel.TQ;
   const int* my_pos = s_sel_pos + tid * KP;
@@ -227,7 +227,7 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
   }
 }
 
-template <int DT, int OT>
+template <int DT, int OT, int MODE>
 __global__ void __launch_bounds__(kTilePix, kWavesPerSimd)
 render_quantile_kernel(ViewArgs v, int n_tiles, qr_params prm, int K, int dim,
                        int32_t* __restrict__ sel_gid_out, float* __restrict__ sel_w_out) {
@@ -235,7 +235,7 @@ render_quantile_kernel(ViewArgs v, int n_tiles, qr_params prm, int K, int dim,
   __shared__ QuantileLds L;
   int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);                            // [256][KP]
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);  // [256][KP]
-  quantile_tile<DT, OT>(to_global(v), xcd_remap(blockIdx.x, n_tiles), K, dim, prm, L, s_sel_gid,
+  quantile_tile<DT, OT, MODE>(to_global(v), xcd_remap(blockIdx.x, n_tiles), K, dim, prm, L, s_sel_gid,
                     s_sel_w, sel_gid_out, sel_w_out);
 }
 
@@ -251,7 +251,7 @@ __device__ __forceinline__ uint32_t queue_begin(int64_t n_items, int q) {
   return static_cast<uint32_t>(n_items * q / kXcdQueues);
 }
 
-template <int DT, int OT>
+template <int DT, int OT, int MODE>
 __global__ void __launch_bounds__(kTilePix, kWavesPerSimd)
 render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t* __restrict__ schedule,
                                int64_t n_items, uint32_t* __restrict__ counter, qr_params prm,
@@ -286,7 +286,7 @@ render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t
     if (item >= n_items) break;
     const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[item]);
     const GView v = to_global(view_args(views[packed >> kViewShift]));
-    quantile_tile<DT, OT>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
+    quantile_tile<DT, OT, MODE>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
                       nullptr, nullptr);
   }
 }
@@ -295,7 +295,7 @@ render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t
 // dealt to the XCDs in contiguous runs of the schedule (neighbouring tiles of
 // a view share L2 contents); workgroups retire as they finish, so work on
 // other streams can take their slots.
-template <int DT, int OT>
+template <int DT, int OT, int MODE>
 __global__ void __launch_bounds__(kTilePix, kWavesPerSimd)
 render_quantile_batched_grid_kernel(const qr_view* __restrict__ views,
                                     const uint32_t* __restrict__ schedule, int n_items,
@@ -306,7 +306,7 @@ render_quantile_batched_grid_kernel(const qr_view* __restrict__ views,
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);
   const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[xcd_remap(blockIdx.x, n_items)]);
   const GView v = to_global(view_args(views[packed >> kViewShift]));
-  quantile_tile<DT, OT>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
+  quantile_tile<DT, OT, MODE>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
                     nullptr, nullptr);
 }
 
@@ -318,22 +318,23 @@ __global__ void reset_counter_kernel(uint32_t* __restrict__ c) {
 
 using namespace qr;
 
-// Instantiates QR_LAUNCH(feature dtype, output dtype) for the runtime pair.
-#define QR_DISPATCH(dt, ot)                                  \
-  do {                                                       \
-    if ((ot) == QR_BF16) {                                   \
-      switch (dt) {                                          \
-        case QR_F32: QR_LAUNCH(QR_F32, QR_BF16); break;      \
-        case QR_BF16: QR_LAUNCH(QR_BF16, QR_BF16); break;    \
-        default: QR_LAUNCH(QR_FP8_E4M3, QR_BF16); break;     \
-      }                                                      \
-    } else {                                                 \
-      switch (dt) {                                          \
-        case QR_F32: QR_LAUNCH(QR_F32, QR_F32); break;       \
-        case QR_BF16: QR_LAUNCH(QR_BF16, QR_F32); break;     \
-        default: QR_LAUNCH(QR_FP8_E4M3, QR_F32); break;      \
-      }                                                      \
-    }                                                        \
+// Instantiates QR_LAUNCH(feature dtype, output dtype, selection rule) for the
+// runtime triple.
+#define QR_DISPATCH_DT(dt, OT, SM)                        \
+  switch (dt) {                                           \
+    case QR_F32: QR_LAUNCH(QR_F32, OT, SM); break;        \
+    case QR_BF16: QR_LAUNCH(QR_BF16, OT, SM); break;      \
+    default: QR_LAUNCH(QR_FP8_E4M3, OT, SM); break;       \
+  }
+#define QR_DISPATCH(dt, ot, sm)                                                   \
+  do {                                                                            \
+    if ((sm) == QR_SELECT_STRATIFIED) {                                           \
+      if ((ot) == QR_BF16) { QR_DISPATCH_DT(dt, QR_BF16, QR_SELECT_STRATIFIED) } \
+      else { QR_DISPATCH_DT(dt, QR_F32, QR_SELECT_STRATIFIED) }                  \
+    } else {                                                                      \
+      if ((ot) == QR_BF16) { QR_DISPATCH_DT(dt, QR_BF16, QR_SELECT_QUANTILE) }   \
+      else { QR_DISPATCH_DT(dt, QR_F32, QR_SELECT_QUANTILE) }                    \
+    }                                                                             \
   } while (0)
 
 extern "C" int qr_render_quantile(void* stream, int32_t width, int32_t height,
@@ -358,10 +359,10 @@ extern "C" int qr_render_quantile(void* stream, int32_t width, int32_t height,
   const ViewArgs v{width, height, tile_offsets, sorted_gid, reinterpret_cast<const float2*>(means2d),
                    reinterpret_cast<const float4*>(conic_opacity), features, feature_scale, out, T_q,
                    n_sel};
-#define QR_LAUNCH(DT, OT)                                                                          \
-  hipLaunchKernelGGL((render_quantile_kernel<DT, OT>), dim3(n_tiles), dim3(kTilePix), lds, s, v,    \
+#define QR_LAUNCH(DT, OT, SM)                                                                         \
+  hipLaunchKernelGGL((render_quantile_kernel<DT, OT, SM>), dim3(n_tiles), dim3(kTilePix), lds, s, v,    \
                      n_tiles, *prm, K, dim, sel_gid, sel_w)
-  QR_DISPATCH(dtype, prm->out_dtype);
+  QR_DISPATCH(dtype, prm->out_dtype, prm->selection);
 #undef QR_LAUNCH
   return check_launch("qr_render_quantile");
 }
@@ -391,24 +392,26 @@ extern "C" int qr_render_quantile_batched(void* stream, int32_t n_views, const q
     return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: need 0 < alpha_min <= alpha_max < 1");
   if (prm->out_dtype != QR_F32 && prm->out_dtype != QR_BF16)
     return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile_batched: unknown output dtype %d", prm->out_dtype);
+  if (prm->selection != QR_SELECT_QUANTILE && prm->selection != QR_SELECT_STRATIFIED)
+    return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile_batched: unknown selection rule %d", prm->selection);
   if (n_items == 0) return QR_OK;
   hipStream_t s = as_stream(stream);
   const size_t lds = static_cast<size_t>(kTilePix) * ((K + 3) & ~3) * (sizeof(int) + sizeof(float));
   if (n_workgroups == 0) {
     const int ni = static_cast<int>(n_items);
-#define QR_LAUNCH(DT, OT)                                                                          \
-  hipLaunchKernelGGL((render_quantile_batched_grid_kernel<DT, OT>), dim3(ni), dim3(kTilePix), lds, \
+#define QR_LAUNCH(DT, OT, SM)                                                                         \
+  hipLaunchKernelGGL((render_quantile_batched_grid_kernel<DT, OT, SM>), dim3(ni), dim3(kTilePix), lds, \
                      s, views, schedule, ni, *prm, K, dim)
-    QR_DISPATCH(dtype, prm->out_dtype);
+    QR_DISPATCH(dtype, prm->out_dtype, prm->selection);
 #undef QR_LAUNCH
     return check_launch("qr_render_quantile_batched");
   }
   auto* counter = static_cast<uint32_t*>(workspace);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
-#define QR_LAUNCH(DT, OT)                                                                          \
-  hipLaunchKernelGGL((render_quantile_batched_kernel<DT, OT>), dim3(n_workgroups), dim3(kTilePix),  \
+#define QR_LAUNCH(DT, OT, SM)                                                                         \
+  hipLaunchKernelGGL((render_quantile_batched_kernel<DT, OT, SM>), dim3(n_workgroups), dim3(kTilePix),  \
                      lds, s, views, schedule, n_items, counter, *prm, K, dim)
-  QR_DISPATCH(dtype, prm->out_dtype);
+  QR_DISPATCH(dtype, prm->out_dtype, prm->selection);
 #undef QR_LAUNCH
   return check_launch("qr_render_quantile_batched");
 }

@@ -349,7 +349,7 @@ __device__ __forceinline__ void quantile_backward_tile(const GView& v, const GGr
   const int lo = static_cast<int>(v.tile_offsets[tile]);
   const int hi = static_cast<int>(v.tile_offsets[tile + 1]);
   const int KP = (K + 3) & ~3;
-  const PixelSel sel = quantile_walk(v, lo, hi, K, pxc, pyc, inside, prm, B, s_sel_pos, s_sel_w, KP);
+  const PixelSel sel = quantile_walk<QR_SELECT_QUANTILE>(v, lo, hi, K, pxc, pyc, inside, prm, B, s_sel_pos, s_sel_w, KP);
   const int ns = sel.ns;
   const int* my_pos = s_sel_pos + tid * KP;
   const float* my_w = s_sel_w + tid * KP;
@@ -571,6 +571,8 @@ extern "C" int qr_render_quantile_backward(void* stream, int32_t width, int32_t 
   if (rc != QR_OK) return rc;
   if (K < 1 || K > QR_MAX_K)
     return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile_backward: K = %d outside [1, %d]", K, QR_MAX_K);
+  if (prm->selection != QR_SELECT_QUANTILE)
+    return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile_backward: the quantile selection only");
   const int tiles_x = static_cast<int>(ceil_div(width, kTile));
   const int tiles_y = static_cast<int>(ceil_div(height, kTile));
   const int n_tiles = tiles_x * tiles_y;
@@ -615,6 +617,8 @@ extern "C" int qr_render_quantile_batched_backward(void* stream, int32_t n_views
     return fail(QR_ERR_UNSUPPORTED, "%s: dim = %d", name, dim);
   if (!(prm->alpha_min > 0.f) || !(prm->alpha_max >= prm->alpha_min) || !(prm->alpha_max < 1.f))
     return fail(QR_ERR_INVALID_ARG, "%s: need 0 < alpha_min <= alpha_max < 1", name);
+  if (prm->selection != QR_SELECT_QUANTILE)
+    return fail(QR_ERR_UNSUPPORTED, "%s: the quantile selection only", name);
   if (n_items == 0) return QR_OK;
   hipStream_t s = as_stream(stream);
   const size_t lds = bwd_dynamic_lds(K);

@@ -25,10 +25,11 @@ class RenderParams:
     dilation: float = 0.3
     guard: float = 1.3
     out_dtype: int = L.QR_F32  # Q-Render feature maps: L.QR_F32 or L.QR_BF16
+    selection: int = L.QR_SELECT_QUANTILE  # or L.QR_SELECT_STRATIFIED (Stratified-K)
 
     def c(self) -> L.qr_params:
         return L.make_params(self.alpha_min, self.alpha_max, self.T_eps, self.dilation, self.guard,
-                             self.out_dtype)
+                             self.out_dtype, self.selection)
 
 
 def tiles_of(width: int, height: int):

@@ -115,6 +115,16 @@ def test_render_validation(L):
     assert rc == L.QR_ERR_UNSUPPORTED and "float32 output" in L.last_error()
     rc = lib.qr_render_quantile_batched(None, 1, d, ctypes.byref(bad_out), 8, 0, 16, d, 10, 0, None, 0)
     assert rc == L.QR_ERR_UNSUPPORTED
+    bad_sel = L.make_params(selection=5)
+    rc = lib.qr_render_quantile(None, 64, 64, ctypes.byref(bad_sel), 8, d, d, d, d, d, 0, None, 16, d,
+                                None, None, None, None)
+    assert rc == L.QR_ERR_UNSUPPORTED and "selection" in L.last_error()
+    rc = lib.qr_render_quantile_batched(None, 1, d, ctypes.byref(bad_sel), 8, 0, 16, d, 10, 0, None, 0)
+    assert rc == L.QR_ERR_UNSUPPORTED
+    strat = L.make_params(selection=L.QR_SELECT_STRATIFIED)
+    rc = lib.qr_render_quantile_backward(None, 64, 64, ctypes.byref(strat), 8, d, d, d, d, d, 0, None,
+                                         16, d, d, d, d)
+    assert rc == L.QR_ERR_UNSUPPORTED
     rc = lib.qr_quantize_features(None, 10, 16, d, 0, d, None)
     assert rc == L.QR_ERR_UNSUPPORTED
     rc = lib.qr_quantize_features(None, 10, 16, d, 2, d, None)
