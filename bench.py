@@ -405,6 +405,29 @@ def run_room(args):
                                   "bytes_per_launch": round(bytes_bf)}}
         del states_bf, outs_bf
 
+    # side result: Stratified-K (Appendix) on the same binned poses, the
+    # batched launch alone (its front is the same as Q-Render's)
+    strat_side = None
+    if not args.renders_only:
+        from paper_2512_20927_amd.batched import BatchedQuantile
+        bq_s = BatchedQuantile(states[0].bq._views, K, D, L.QR_F32,
+                               qr.RenderParams(selection=L.QR_SELECT_STRATIFIED).c())
+        tuned_s, _ = autotune(bq_s, wg_per_cu=(0, 3, 8), use_cache=False)
+        for _ in range(args.warmup):
+            bq_s.render(tuned_s["schedule"], tuned_s["wg_per_cu"])
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(args.steps):
+            bq_s.render(tuned_s["schedule"], tuned_s["wg_per_cu"])
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms_s = ev[0].elapsed_time(ev[1]) / args.steps
+        strat_side = {"render_ms": round(ms_s, 4), "render_frames_per_s": round(n_views / (ms_s * 1e-3), 2),
+                      "quantile_render_frames_per_s": round(n_views / (k_seq * 1e-3), 2),
+                      "batched_launch": {k: tuned_s[k] for k in ("schedule", "wg_per_cu")}}
+        del bq_s
+
     cpu = None
     if args.cpu_budget > 0 and not args.renders_only:
         cpu = cpu_reference(sc, cams[0], K, args.cpu_budget)
@@ -446,6 +469,7 @@ def run_room(args):
                      "bytes_per_launch": round(bytes_batch), "frames_per_launch": n_views},
         "cpu_baseline": cpu,
         "bf16_output": bf16_side,
+        "stratified_k": strat_side,
         "autotune_ms": {k: round(v, 3) for k, v in tune_ms.items()},
         "setup_s": round(t_setup, 1),
     }
