@@ -111,7 +111,8 @@ typedef struct qr_params {
    * transmittance after every Gaussian the dense blend composites (with its
    * T_eps stop); then t_m = clip(mu + sigma Phi^-1(1 - m/(K+1)), 0, 1),
    * evaluated in double and rounded once to float, and Algorithm 1 runs with
-   * these thresholds, ending once all K are consumed). The backward passes
+   * these thresholds over the same Gaussians, ending at the dense stop or
+   * once all K are consumed). The backward passes
    * support QR_SELECT_QUANTILE only. */
   int32_t selection;
 } qr_params;

@@ -21,8 +21,10 @@ Readings (the appendix gives no formula):
     any ray with an on-ray Gaussian (a ray with none selects nothing);
   * sigma is the population standard deviation;
   * thresholds are clipped to [0, 1]; crossings compare with "<" as in
-    Algorithm 1, and the walk ends once all K thresholds are consumed (the
-    counterpart of Algorithm 1's stop test) or the list ends;
+    Algorithm 1; the second pass examines the Gaussians the first pass
+    sampled (it ends where the dense blend stops, at T_test < T_eps, like
+    the first pass) and ends earlier once all K thresholds are consumed (the
+    counterpart of Algorithm 1's stop test);
   * the output is normalised by 1 - T^Q as in Sec. 4.2 (0 if nothing is
     selected).
 Phi^{-1} is scipy.special.ndtri (a library step).
@@ -108,6 +110,8 @@ def render_stratified(proj, sorted_gid, tile_offsets, features, width, height, K
             for i in np.nonzero(on)[0]:
                 a = a_all[i]
                 T_test = T * (1.0 - a)
+                if T_test < params.T_eps:  # the dense stop ends the sampled ray
+                    break
                 live = thr[:K][thr[:K] > 0.0]
                 if live.size:
                     marg = min(marg, float(np.min(np.abs(T_test - live) / live)))

@@ -115,7 +115,8 @@ struct PixelSel {
 // MODE QR_SELECT_STRATIFIED (Stratified-K, Appendix): a first pass over the
 // list estimates the mean and spread of the ray's transmittance values (T_0 =
 // 1 and T after every Gaussian the dense blend composites, with its T_eps
-// stop; sums in double) and the thresholds are the ray's own.
+// stop; sums in double) and the thresholds are the ray's own; the second
+// pass examines the same Gaussians (it also ends at the dense stop).
 template <int MODE, class WalkLds>
 __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi, int K, float pxc,
                                                   float pyc, bool inside, const qr_params& prm,
@@ -141,20 +142,35 @@ __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi
         const f32x4 c = v.conic_opacity[g];
         L.mean[tid] = make_float2(m.x, m.y);
         L.co[tid] = make_float4(c.x, c.y, c.z, c.w);
+      } else {  // padding record: opacity 0 is below alpha_min on every ray
+        L.mean[tid] = make_float2(0.f, 0.f);
+        L.co[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
       __syncthreads();
-      const int cnt = min(kTilePix, hi - batch);
-      for (int j = 0; j < cnt && !stop; ++j) {
-        const float alpha = gauss_alpha(L.mean[j], L.co[j], pxc, pyc, amax);
-        if (alpha < amin) continue;
-        const float T_test = T1 * (1.f - alpha);
-        if (T_test < prm.T_eps) {
-          stop = true;
-        } else {
-          T1 = T_test;
-          s1 += T1;
-          s2 += static_cast<double>(T1) * T1;
-          ++n;
+      constexpr int kU = 8;  // records read from LDS per round trip
+      const int cnt_pad = (min(kTilePix, hi - batch) + kU - 1) & ~(kU - 1);
+      for (int j = 0; j < cnt_pad; j += kU) {
+        if (__all(stop)) break;
+        float2 rm[kU];
+        float4 rc[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          rm[u] = L.mean[j + u];
+          rc[u] = L.co[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const float alpha = gauss_alpha(rm[u], rc[u], pxc, pyc, amax);
+          if (stop || alpha < amin) continue;
+          const float T_test = T1 * (1.f - alpha);
+          if (T_test < prm.T_eps) {
+            stop = true;
+          } else {
+            T1 = T_test;
+            s1 += T1;
+            s2 += static_cast<double>(T1) * T1;
+            ++n;
+          }
         }
       }
     }
@@ -207,6 +223,10 @@ __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi
         const float alpha = gauss_alpha(rm[u], rc[u], pxc, pyc, amax);
         if (done || alpha < amin) continue;  // finished, or not on this pixel's ray
         const float T_test = T * (1.f - alpha);
+        if (MODE == QR_SELECT_STRATIFIED && T_test < prm.T_eps) {  // the sampled ray ends here
+          done = true;
+          continue;
+        }
         if (T_test < thr_k) {  // crossing: a quantile Gaussian
           my_pos[ns] = batch + j + u;
           my_w[ns] = TQ * alpha;

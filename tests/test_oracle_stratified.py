@@ -60,15 +60,16 @@ def _one_ray_case(alphas, dim=3, seed=0):
     return proj, np.arange(n), np.array([0, n]), feats
 
 
-def _interval_selection(alphas, thr):
+def _interval_selection(alphas, thr, T_eps):
     """Closed form: entry i is selected iff a threshold lies in (T_after_i,
-    T_before_i]; the walk ends after the entry that consumes the last one."""
+    T_before_i]; the walk ends after the entry that consumes the last one, or
+    at the first entry whose T_after falls below T_eps (not examined)."""
     a = np.asarray(alphas, np.float64)
     T_after = np.cumprod(1.0 - a)
     T_before = np.concatenate([[1.0], T_after[:-1]])
     sel, consumed = [], 0
     for i in range(a.size):
-        if consumed == len(thr):
+        if consumed == len(thr) or T_after[i] < T_eps:
             break
         hit = [m for m in range(len(thr)) if T_after[i] < thr[m] <= T_before[i]]
         if hit:
@@ -83,7 +84,7 @@ def test_selection_matches_interval_form_with_the_rays_thresholds(K):
     prm = oracle.RenderParams()
     for trial in range(60):
         n = int(rng.integers(1, 40))
-        alphas = rng.uniform(0.02, 0.6, n)
+        alphas = rng.uniform(0.02, 0.6, n) if trial % 2 else rng.uniform(0.3, 0.95, n)
         proj, gids, offs, feats = _one_ray_case(alphas, seed=trial)
         r = oracle.render_stratified(proj, gids, offs, feats, 1, 1, K, prm)
         # statistics written out independently: T_0 = 1 and the composited T
@@ -92,7 +93,7 @@ def test_selection_matches_interval_form_with_the_rays_thresholds(K):
         last = np.argmin(keep) if not keep.all() else T.size
         vals = T[:last]
         thr = oracle.stratified_thresholds(vals.mean(), vals.std(), K)
-        want = _interval_selection(alphas, list(thr))
+        want = _interval_selection(alphas, list(thr), prm.T_eps)
         got = [int(g) for g in r["sel_gid"][0, 0] if g >= 0]
         assert got == want, (trial, alphas, thr)
         assert r["n_sel"][0, 0] <= K
