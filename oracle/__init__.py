@@ -18,6 +18,8 @@ paper's definitions:
 * ``selection`` - the closed "interval" form of the quantile selection.
 * ``stratified`` - the Stratified-K variant (Appendix): per-ray thresholds
                   from the ray's transmittance statistics.
+* ``devoxelize`` - per-Gaussian features as the max (or mean) of the
+                  predictions of the voxels each Gaussian covers.
 * ``backward``  - analytic gradients of both renderers.
 * ``quant``     - bfloat16 / OCP e4m3 storage codes for the feature table.
 
@@ -32,6 +34,7 @@ from .binning import bin_sort  # noqa: F401
 from .render import render_dense, render_quantile, quantile_thresholds  # noqa: F401
 from .brute import brute_force_render  # noqa: F401
 from .selection import interval_selection  # noqa: F401
+from .devoxelize import devoxelize, devoxelize_backward  # noqa: F401
 from .stratified import render_stratified, stratified_thresholds, transmittance_stats  # noqa: F401
 from .backward import dense_backward, quantile_backward  # noqa: F401
 from . import quant  # noqa: F401
