@@ -48,77 +48,13 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="profiling aid: first run a plain 1 GiB device copy, whose known "
                          "traffic calibrates the FETCH_SIZE / WRITE_SIZE counters")
-    ap.add_argument("--workload", default="room", choices=["room", "precision", "diff", "batched"],
+    ap.add_argument("--workload", default="room", choices=["room", "precision", "diff", "batched", "devox"],
                     help="room (default, the headline metric); precision: 1M Gaussians at "
                          "1296x968 with bf16 features, K in {4,8,16}; diff: 500k Gaussians, bf16, "
                          "forward+backward through autograd; batched: 32 views of 4 scenes "
-                         "(0.3M-3M Gaussians) at 1280x720, fp8 e4m3 features, one persistent launch")
+                         "(0.3M-3M Gaussians) at 1280x720, fp8 e4m3 features, one persistent launch; "
+                         "devox: de-voxelisation (segment max) of 512-D voxel predictions to 200k Gaussians")
     return ap.parse_args()
-
-
-class FrameRunner:
-    """Preallocated buffers and the per-frame launch sequence of one lane
-    (frames of a lane run in order on the lane's stream)."""
-
-    def __init__(self, qr, L, scene_t, cams, K, capacity, dim, feats=None, scale=None):
-        import torch
-        self.qr, self.L, self.K = qr, L, K
-        self.s = scene_t
-        self.feats = scene_t["feats"] if feats is None else feats
-        self.scale = scale
-        self.cams = [L.make_camera(c) for c in cams]
-        self.W, self.H = cams[0].width, cams[0].height
-        n = scene_t["means"].shape[0]
-        self.pr = qr.render.alloc_projected(n)
-        self.binner = qr.Binner(n, self.W, self.H, capacity)
-        self.prm = qr.RenderParams(out_dtype=L.QR_F32 if out_dtype is None else out_dtype).c()
-        dev = "cuda"
-        self.out = torch.empty(self.H, self.W, dim, dtype=torch.float32, device=dev)
-        self.aux_f = torch.empty(self.H, self.W, dtype=torch.float32, device=dev)
-        self.aux_i = torch.empty(self.H, self.W, dtype=torch.int32, device=dev)
-
-    def front(self, v):
-        s, pr, L = self.s, self.pr, self.L
-        L.qr_project(s["means"], s["scales"], s["quats"], s["opacity"], self.cams[v], self.prm,
-                     pr.means2d, pr.conic_opacity, pr.depth, pr.tile_rect, pr.tiles_touched)
-        return self.binner(pr)
-
-    def render_q(self, bins):
-        self.L.qr_render_quantile(self.W, self.H, self.prm, self.K, bins.tile_offsets, bins.sorted_gid,
-                                  self.pr.means2d, self.pr.conic_opacity, self.feats, self.scale,
-                                  self.out, self.aux_f, self.aux_i)
-
-    def render_d(self, bins):
-        self.L.qr_render_dense(self.W, self.H, self.prm, bins.tile_offsets, bins.sorted_gid,
-                               self.pr.means2d, self.pr.conic_opacity, self.feats, self.scale,
-                               self.out, self.aux_f, self.aux_i)
-
-
-def timed(runner, which, steps, warmup, n_views):
-    """Runs `steps` steps of n_views frames on one stream; HIP events bracket
-    each render launch on the launch stream. Returns (seconds, mean
-    render-kernel ms)."""
-    import torch
-    render = runner.render_q if which == "q" else runner.render_d
-    for _ in range(warmup):
-        for v in range(n_views):
-            render(runner.front(v))
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(steps * n_views)]
-    t0 = time.perf_counter()
-    i = 0
-    for _ in range(steps):
-        for v in range(n_views):
-            bins = runner.front(v)
-            evs[i][0].record()
-            render(bins)
-            evs[i][1].record()
-            i += 1
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    kms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    return dt, kms
 
 
 class BatchState:
@@ -287,7 +223,7 @@ def main():
               "and this build runs on a single MI355X; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     {"room": run_room, "precision": run_precision, "diff": run_diff,
-     "batched": run_batched}[args.workload](args)
+     "batched": run_batched, "devox": run_devox}[args.workload](args)
 
 
 def _base_record(args, value, unit, dtype, workload, ms_per_step):
@@ -583,6 +519,56 @@ def run_diff(args):
                        "backward (autograd, cosine loss); one iteration = one view",
                        1e3 / res["q"])
     rec.update({"dense_value": round(res["d"], 2), "q_over_dense": round(res["q"] / res["d"], 3)})
+    print(json.dumps(rec))
+
+
+def run_devox(args):
+    """De-voxelisation (segment max) of 512-D float32 unique-voxel predictions
+    to the 200k Gaussians of a room-scale scene: each Gaussian covers 1-15
+    voxel slots (uniform), 100k unique voxels; forward with argmax, then the
+    backward. HBM roofline on the algorithmic bytes of the forward."""
+    import torch
+    from paper_2512_20927_amd import _lib as L
+    G, U, C = 200_000, 100_000, 512
+    rng = np.random.default_rng(41)
+    counts = rng.integers(1, 16, G)
+    offs = torch.from_numpy(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)).cuda()
+    M = int(counts.sum())
+    vu = torch.from_numpy(rng.integers(0, U, M).astype(np.int32)).cuda()
+    pred = torch.randn(U, C, device="cuda")
+    out = torch.empty(G, C, device="cuda")
+    arg = torch.empty(G, C, dtype=torch.int32, device="cuda")
+    gout = torch.randn(G, C, device="cuda")
+    grad = torch.zeros(U, C, device="cuda")
+
+    def fwd():
+        L.qr_devoxelize(offs, vu, pred, L.QR_REDUCE_MAX, out, arg)
+
+    def bwd():
+        L.qr_devoxelize_backward(offs, vu, U, L.QR_REDUCE_MAX, gout, arg, grad)
+
+    res = {}
+    for name, fn in (("forward", fwd), ("backward", bwd)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        res[name] = a.elapsed_time(b) / args.steps
+    # offsets + slot indices + one gathered row per slot + output + argmax
+    bytes_fwd = (G + 1) * 8 + M * 4 + M * C * 4 + G * C * 4 * 2
+    achieved = bytes_fwd / (res["forward"] * 1e-3) / 1e9
+    rec = _base_record(args, G / (res["forward"] * 1e-3), "Gaussians/s", "f32",
+                       "devox: 200k Gaussians x 1-15 voxel slots (%d), 100k unique voxels, 512-D, "
+                       "segment max with argmax" % M, res["forward"])
+    rec.update({"forward_ms": round(res["forward"], 4), "backward_ms": round(res["backward"], 4),
+                "roofline": {"bound": "hbm", "kernel": "devoxelize_kernel<0>", "achieved": round(achieved, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                             "traffic": None, "bytes_per_launch": bytes_fwd}})
     print(json.dumps(rec))
 
 

@@ -64,6 +64,12 @@ typedef enum qr_dtype {
   QR_FP8_E4M3 = 2  /* OCP FP8 e4m3 code times a per-Gaussian float32 scale */
 } qr_dtype;
 
+/* Reductions of qr_devoxelize. */
+typedef enum {
+  QR_REDUCE_MAX = 0,
+  QR_REDUCE_MEAN = 1
+} qr_reduce;
+
 /* Threshold rules of the Q-Render selection (qr_params.selection). */
 typedef enum {
   QR_SELECT_QUANTILE = 0,   /* Algorithm 1 */
@@ -412,6 +418,33 @@ int qr_render_quantile_batched_backward(void* stream, int32_t n_views, const qr_
                                         const uint32_t* schedule, int64_t n_items,
                                         int32_t n_workgroups, void* workspace,
                                         size_t workspace_bytes);
+
+/*
+ * qr_devoxelize - per-Gaussian features from voxel predictions (the step that
+ * produces the feature table the renderer reads; Appendix, de-voxelisation):
+ * out[g, c] = reduce over slots m in [offsets[g], offsets[g+1]) of
+ * unique_pred[voxel_unique[m], c], reduce = QR_REDUCE_MAX (ties: the first
+ * slot) or QR_REDUCE_MEAN. offsets: device i64[n_gauss+1]; voxel_unique:
+ * device i32[n_slots]; unique_pred: device f32[n_unique, dim]; out: device
+ * f32[n_gauss, dim]; argmax (max only, may be NULL): device i32[n_gauss, dim],
+ * the slot that gave each maximum (for the backward). A Gaussian with no
+ * (valid) slot gets the zero row and argmax -1. Slot indices outside
+ * [0, n_unique) and offsets outside [0, n_slots] are ignored (checked in the
+ * kernel). dim: a positive multiple of 4, <= QR_MAX_DIM.
+ * qr_devoxelize_backward - ACCUMULATES dL/d(unique_pred) into grad_unique
+ * (device f32[n_unique, dim]; the caller zeroes it) from grad_out (device
+ * f32[n_gauss, dim]): max routes each element to its argmax slot's row, mean
+ * spreads grad / count over the segment. Float atomics: the order of the
+ * additions is unspecified.
+ */
+int qr_devoxelize(void* stream, int64_t n_gauss, int32_t dim, const int64_t* offsets,
+                  const int32_t* voxel_unique, int64_t n_slots, int64_t n_unique,
+                  const float* unique_pred, int32_t reduce, float* out, int32_t* argmax);
+
+int qr_devoxelize_backward(void* stream, int64_t n_gauss, int32_t dim, const int64_t* offsets,
+                           const int32_t* voxel_unique, int64_t n_slots, int64_t n_unique,
+                           int32_t reduce, const float* grad_out, const int32_t* argmax,
+                           float* grad_unique);
 
 /*
  * qr_quantize_features - encodes a float32 feature table f32[N,dim] for

@@ -22,6 +22,7 @@ LIB_PATH = os.environ.get("QRENDER_LIB") or os.path.join(
 QR_OK, QR_ERR_INVALID_ARG, QR_ERR_UNSUPPORTED, QR_ERR_CAPACITY, QR_ERR_HIP = 0, -1, -2, -3, -4
 QR_F32, QR_BF16, QR_FP8_E4M3 = 0, 1, 2
 QR_SELECT_QUANTILE, QR_SELECT_STRATIFIED = 0, 1
+QR_REDUCE_MAX, QR_REDUCE_MEAN = 0, 1
 QR_TILE = 16
 QR_MAX_K = 32
 
@@ -30,7 +31,8 @@ EXPORTED = [
     "qr_bin_sort_workspace_size", "qr_bin_sort", "qr_render_dense", "qr_render_quantile",
     "qr_render_dense_backward", "qr_render_quantile_backward", "qr_quantize_features",
     "qr_render_quantile_batched", "qr_batch_schedule", "qr_project_views", "qr_bin_sort_views",
-    "qr_render_quantile_batched_backward", "qr_autotune_batched",
+    "qr_render_quantile_batched_backward", "qr_autotune_batched", "qr_devoxelize",
+    "qr_devoxelize_backward",
 ]
 QR_BATCH_TILE_BITS = 20
 
@@ -93,6 +95,8 @@ def _load():
         "qr_render_quantile_batched": ([P, i32, P, prm_p, i32, i32, i32, P, i64, i32, P, sz], i32),
         "qr_batch_schedule": ([P, i32, P, P, i64, P, P, sz], i32),
         "qr_render_quantile_batched_backward": ([P, i32, P, P, prm_p, i32, i32, i32, P, i64, i32, P, sz], i32),
+        "qr_devoxelize": ([P, i64, i32, P, P, i64, i64, P, i32, P, P], i32),
+        "qr_devoxelize_backward": ([P, i64, i32, P, P, i64, i64, i32, P, P, P], i32),
         "qr_autotune_batched": ([P, i32, P, prm_p, i32, i32, i32, ctypes.POINTER(ctypes.c_void_p), i32, i64,
                                  ctypes.POINTER(i32), i32, i32, P, sz, ctypes.POINTER(ctypes.c_float),
                                  ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
@@ -441,6 +445,35 @@ def qr_autotune_batched(n_views, views_dev, params, K, dtype_code, dim, schedule
                                     _ptr(workspace) if workspace is not None else None, ws_bytes,
                                     times, ctypes.byref(bi), ctypes.byref(bw)))
     return bi.value, bw.value, [[times[i * nw + j] for j in range(nw)] for i in range(ns)]
+
+
+def qr_devoxelize(offsets, voxel_unique, unique_pred, reduce, out, argmax=None, stream=None):
+    """offsets: int64 [G+1]; voxel_unique: int32 [M]; unique_pred: f32 [U, C];
+    out: f32 [G, C]; argmax: int32 [G, C] or None."""
+    G = offsets.numel() - 1
+    U, C = unique_pred.shape
+    _need(offsets, G + 1, (torch.int64,), "offsets")
+    _need(voxel_unique, voxel_unique.numel(), I32, "voxel_unique")
+    _need(unique_pred, U * C, F32, "unique_pred")
+    _need(out, G * C, F32, "out")
+    _need(argmax, G * C, I32, "argmax")
+    _check(_LIB.qr_devoxelize(_stream(stream), G, C, _ptr(offsets), _ptr(voxel_unique),
+                              voxel_unique.numel(), U, _ptr(unique_pred), reduce, _ptr(out),
+                              _ptr(argmax)))
+
+
+def qr_devoxelize_backward(offsets, voxel_unique, n_unique, reduce, grad_out, argmax, grad_unique,
+                           stream=None):
+    G = offsets.numel() - 1
+    C = grad_out.shape[1]
+    _need(offsets, G + 1, (torch.int64,), "offsets")
+    _need(voxel_unique, voxel_unique.numel(), I32, "voxel_unique")
+    _need(grad_out, G * C, F32, "grad_out")
+    _need(argmax, G * C, I32, "argmax")
+    _need(grad_unique, n_unique * C, F32, "grad_unique")
+    _check(_LIB.qr_devoxelize_backward(_stream(stream), G, C, _ptr(offsets), _ptr(voxel_unique),
+                                       voxel_unique.numel(), n_unique, reduce, _ptr(grad_out),
+                                       _ptr(argmax), _ptr(grad_unique)))
 
 
 def pack_grads(grads) -> bytes:

@@ -30,6 +30,7 @@ SOURCES = [
     "quantize.hip",
     "schedule.hip",
     "autotune.hip",
+    "devoxelize.hip",
 ]
 
 # Packed FP32 instructions are switched off: float code is compiled to

@@ -185,6 +185,20 @@ def test_batched_validation(L):
     assert rc == L.QR_ERR_CAPACITY
 
 
+def test_devoxelize_validation(L):
+    lib = L.lib()
+    d = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    dv = lambda G, C, red, offs=d, vu=d, M=10, out=d: lib.qr_devoxelize(None, G, C, offs, vu, M, 5, d, red, out, None)
+    assert dv(-1, 16, 0) == L.QR_ERR_INVALID_ARG
+    assert dv(10, 6, 0) == L.QR_ERR_UNSUPPORTED  # dim not a multiple of 4
+    assert dv(10, 16, 3) == L.QR_ERR_UNSUPPORTED
+    assert dv(10, 16, 0, offs=None) == L.QR_ERR_INVALID_ARG
+    assert dv(10, 16, 0, out=None) == L.QR_ERR_INVALID_ARG
+    assert dv(0, 16, 0) == L.QR_OK  # nothing to do
+    rc = lib.qr_devoxelize_backward(None, 10, 16, d, d, 10, 5, 0, d, None, d)
+    assert rc == L.QR_ERR_INVALID_ARG  # max needs the argmax slots
+
+
 def test_views_front_validation(L):
     lib = L.lib()
     prm = L.make_params()
