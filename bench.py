@@ -559,13 +559,17 @@ def run_devox(args):
         b.record()
         torch.cuda.synchronize()
         res[name] = a.elapsed_time(b) / args.steps
-    # offsets + slot indices + one gathered row per slot + output + argmax
-    bytes_fwd = (G + 1) * 8 + M * 4 + M * C * 4 + G * C * 4 * 2
+    # compulsory HBM bytes: offsets + slot indices + every unique row once +
+    # output + argmax (a row gathered again by another slot can come from
+    # the caches; the gathered bytes are reported beside)
+    bytes_fwd = (G + 1) * 8 + M * 4 + U * C * 4 + G * C * 4 * 2
+    gathered = M * C * 4
     achieved = bytes_fwd / (res["forward"] * 1e-3) / 1e9
     rec = _base_record(args, G / (res["forward"] * 1e-3), "Gaussians/s", "f32",
                        "devox: 200k Gaussians x 1-15 voxel slots (%d), 100k unique voxels, 512-D, "
                        "segment max with argmax" % M, res["forward"])
     rec.update({"forward_ms": round(res["forward"], 4), "backward_ms": round(res["backward"], 4),
+                "gathered_row_bytes": gathered,
                 "roofline": {"bound": "hbm", "kernel": "devoxelize_kernel<0>", "achieved": round(achieved, 1),
                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                              "traffic": None, "bytes_per_launch": bytes_fwd}})
