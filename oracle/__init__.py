@@ -20,6 +20,7 @@ paper's definitions:
                   from the ray's transmittance statistics.
 * ``devoxelize`` - per-Gaussian features as the max (or mean) of the
                   predictions of the voxels each Gaussian covers.
+* ``sh``        - view-dependent RGB from spherical-harmonic coefficients.
 * ``backward``  - analytic gradients of both renderers.
 * ``quant``     - bfloat16 / OCP e4m3 storage codes for the feature table.
 
@@ -34,6 +35,7 @@ from .binning import bin_sort  # noqa: F401
 from .render import render_dense, render_quantile, quantile_thresholds  # noqa: F401
 from .brute import brute_force_render  # noqa: F401
 from .selection import interval_selection  # noqa: F401
+from .sh import sh_basis, sh_to_rgb  # noqa: F401
 from .devoxelize import devoxelize, devoxelize_backward  # noqa: F401
 from .stratified import render_stratified, stratified_thresholds, transmittance_stats  # noqa: F401
 from .backward import dense_backward, quantile_backward  # noqa: F401
