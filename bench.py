@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="profiling aid: first run a plain 1 GiB device copy, whose known "
                          "traffic calibrates the FETCH_SIZE / WRITE_SIZE counters")
-    ap.add_argument("--workload", default="room", choices=["room", "precision", "diff", "batched", "devox"],
+    ap.add_argument("--workload", default="room", choices=["room", "precision", "diff", "batched", "devox", "rgb"],
                     help="room (default, the headline metric); precision: 1M Gaussians at "
                          "1296x968 with bf16 features, K in {4,8,16}; diff: 500k Gaussians, bf16, "
                          "forward+backward through autograd; batched: 32 views of 4 scenes "
@@ -103,6 +103,39 @@ class BatchState:
                                    pr.conic_opacity, self.s["feats"], self.scale, self.outs[v],
                                    self.aux_f[v], self.aux_i[v])
 
+
+
+class RgbState(BatchState):
+    """BatchState whose feature table is per pose: the view-dependent colours
+    of degree-3 spherical harmonics, evaluated for every pose in the front
+    (columns 0..2 of a 16-wide table, the rest zero)."""
+
+    def __init__(self, qr, L, scene_t, sh, cams, W, H, capacity, outs, aux_f, aux_i, K):
+        import torch
+        n = scene_t["means"].shape[0]
+        self.sh, self.cams_py = sh, cams
+        self.rgb = [torch.empty(n, 16, device="cuda") for _ in cams]
+        super().__init__(qr, L, scene_t, cams, W, H, capacity, outs, aux_f, aux_i, K, 16)
+
+    def make_bq(self, K):
+        from paper_2512_20927_amd.batched import BatchedQuantile
+        views = [dict(tile_offsets=b.tile_offsets, sorted_gid=b.sorted_gid, means2d=pr.means2d,
+                      conic_opacity=pr.conic_opacity, features=self.rgb[v], feature_scale=None,
+                      out=self.outs[v], T_q=self.aux_f[v], n_sel=self.aux_i[v], width=self.W,
+                      height=self.H)
+                 for v, (pr, b) in enumerate(self.per_view)]
+        return BatchedQuantile(views, K, 16, self.L.QR_F32, self.prm)
+
+    def front(self):
+        for v, cam in enumerate(self.cams_py):
+            self.L.qr_sh_to_rgb(self.s["means"], self.sh, 3, cam, self.rgb[v])
+        super().front()
+
+    def render_dense(self):
+        for v, (pr, b) in enumerate(self.per_view):
+            self.L.qr_render_dense(self.W, self.H, self.prm, b.tile_offsets, b.sorted_gid, pr.means2d,
+                                   pr.conic_opacity, self.rgb[v], None, self.outs[v], self.aux_f[v],
+                                   self.aux_i[v])
 
 def timed_batched(states, steps, warmup, schedule, wg_per_cu, overlap=True):
     """`steps` steps of (front, batched render). With overlap, a software
@@ -223,7 +256,7 @@ def main():
               "and this build runs on a single MI355X; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     {"room": run_room, "precision": run_precision, "diff": run_diff,
-     "batched": run_batched, "devox": run_devox}[args.workload](args)
+     "batched": run_batched, "devox": run_devox, "rgb": run_rgb}[args.workload](args)
 
 
 def _base_record(args, value, unit, dtype, workload, ms_per_step):
@@ -312,8 +345,8 @@ def run_room(args):
     # bracket the batched launch alone (in the overlapped run the front of the
     # next step shares the GPU with it)
     achieved = bytes_batch / (k_seq * 1e-3) / 1e9
-    kernel = ("render_quantile_batched_grid_kernel<0, 0>" if tuned["wg_per_cu"] == 0
-              else "render_quantile_batched_kernel<0, 0>")
+    kernel = ("render_quantile_batched_grid_kernel<0, 0, 0>" if tuned["wg_per_cu"] == 0
+              else "render_quantile_batched_kernel<0, 0, 0>")
     traffic = measured_traffic(kernel, "room")
 
     # side result: the same steps writing bfloat16 maps (half the output
@@ -575,6 +608,68 @@ def run_devox(args):
                              "traffic": None, "bytes_per_launch": bytes_fwd}})
     print(json.dumps(rec))
 
+
+
+def run_rgb(args):
+    """RGB use of Q-Render (Appendix, "Rendering RGB"): the room scene (200k
+    Gaussians, 640x480, 16 poses) with synthetic degree-3 spherical-harmonic
+    colours. A step: colours of every pose, projection and binning of every
+    pose, one batched Q-Render launch (16-wide table, 3 colour columns).
+    Reports frames/s per K, the dense blend, and PSNR of Q-Render against the
+    dense blend (no ground-truth images exist for a synthetic scene)."""
+    import torch
+    import paper_2512_20927_amd as qr
+    from paper_2512_20927_amd import _lib as L
+    from paper_2512_20927_amd.batched import autotune
+    import synth
+    cfg = synth.CONFIGS["room"]
+    sc = synth.make_room(cfg["n"], cfg["seed"], dim=16)
+    cams = synth.room_poses(cfg["pose_seeds"][:args.poses], cfg["width"], cfg["height"], cfg["fx"])
+    W, H = cfg["width"], cfg["height"]
+    s = _scene_tensors(sc, torch)
+    sh = torch.from_numpy(synth.sh_coefficients(sc.n, 3, seed=cfg["seed"] + 1)).cuda()
+    pv = qr.project_views(s["means"], s["scales"], s["quats"], s["opacity"], cams)
+    capacity = int(qr.count_pairs(pv) * 1.05) + 1024
+    del pv
+    nv = len(cams)
+    outs = [torch.empty(H, W, 16, device="cuda") for _ in range(nv)]
+    aux_f = [torch.empty(H, W, device="cuda") for _ in range(nv)]
+    aux_i = [torch.empty(H, W, dtype=torch.int32, device="cuda") for _ in range(nv)]
+    states = [RgbState(qr, L, s, sh, cams, W, H, capacity, outs, aux_f, aux_i, 8) for _ in range(2)]
+    for st in states:
+        st.front()
+    torch.cuda.synchronize()
+    frames = args.steps * nv
+    # dense reference images and T after the last Gaussian (for the record)
+    states[0].render_dense()
+    torch.cuda.synchronize()
+    ref = [o[..., :3].clamp(0, 1).clone() for o in outs]
+    T_final = float(torch.stack([a.clone() for a in aux_f]).mean().item())
+    dt_d = timed_dense(states[0], args.steps, args.warmup)
+    per_k, psnr, render_ms = {}, {}, {}
+    for K in (4, 8, 16):
+        for st in states:
+            st.bq = st.make_bq(K)
+        tuned, _ = autotune(states[0].bq, wg_per_cu=(0, 3, 8), use_cache=False)
+        states[0].front()
+        states[0].bq.render(tuned["schedule"], tuned["wg_per_cu"])
+        torch.cuda.synchronize()
+        mse = float(torch.stack([((o[..., :3].clamp(0, 1) - r) ** 2).mean() for o, r in zip(outs, ref)])
+                    .mean().item())
+        psnr[str(K)] = round(10 * np.log10(1.0 / max(mse, 1e-20)), 2)
+        dt, kms = timed_batched(states, args.steps, args.warmup, tuned["schedule"], tuned["wg_per_cu"])
+        per_k[str(K)] = round(frames / dt, 2)
+        render_ms[str(K)] = round(kms, 4)
+    d_fps = frames / dt_d
+    rec = _base_record(args, per_k["8"], "frames/s", "f32",
+                       "rgb: 200k Gaussians, 640x480, fx=fy=577, degree-3 spherical-harmonic colours "
+                       "(synthetic), %d poses per step; value = Q-Render K=8" % nv,
+                       1e3 * frames / per_k["8"] / args.steps)
+    rec.update({"q_fps_per_K": per_k, "dense_value": round(d_fps, 2),
+                "q_over_dense": round(per_k["8"] / d_fps, 3),
+                "psnr_q_vs_dense_db": psnr, "dense_T_final_mean": round(T_final, 5),
+                "render_ms": {"quantile_batched_launch_per_K": render_ms}})
+    print(json.dumps(rec))
 
 def run_batched(args):
     """32 views over 4 scenes (0.3M, 0.8M, 1.5M, 3M Gaussians) at 1280x720,

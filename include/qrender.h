@@ -420,6 +420,23 @@ int qr_render_quantile_batched_backward(void* stream, int32_t n_views, const qr_
                                         size_t workspace_bytes);
 
 /*
+ * qr_sh_to_rgb - view-dependent colours of 3D-GS Gaussians for the RGB use of
+ * Q-Render (Appendix, "Rendering RGB"): per Gaussian, with d the unit vector
+ * from the camera centre (-R_cw^T t) to the mean, colour_ch = 1/2 +
+ * sum over the first (degree+1)^2 real orthonormal spherical harmonics
+ * Y_lm(d) (m = -l..l, index l^2+l+m, with the Condon-Shortley phase
+ * (-1)^m: the sign convention of 3D-GS coefficients; d = 0 for a mean at
+ * the camera centre) of
+ * sh[i, l^2+l+m, ch], clipped below at 0. means3d: device f32[n,3]; sh:
+ * device f32[n, coef_stride, 3], coef_stride >= (degree+1)^2; cam: host.
+ * Writes out (device f32[n, out_dim], out_dim >= 3): the colour in columns
+ * 0..2, zeros in the rest (a feature table for the renderers, whose dim must
+ * be a multiple of 16). degree in [0, 3].
+ */
+int qr_sh_to_rgb(void* stream, int64_t n, int32_t degree, const float* means3d, const float* sh,
+                 int32_t coef_stride, const qr_camera* cam, float* out, int32_t out_dim);
+
+/*
  * qr_devoxelize - per-Gaussian features from voxel predictions (the step that
  * produces the feature table the renderer reads; Appendix, de-voxelisation):
  * out[g, c] = reduce over slots m in [offsets[g], offsets[g+1]) of

@@ -32,7 +32,7 @@ EXPORTED = [
     "qr_render_dense_backward", "qr_render_quantile_backward", "qr_quantize_features",
     "qr_render_quantile_batched", "qr_batch_schedule", "qr_project_views", "qr_bin_sort_views",
     "qr_render_quantile_batched_backward", "qr_autotune_batched", "qr_devoxelize",
-    "qr_devoxelize_backward",
+    "qr_devoxelize_backward", "qr_sh_to_rgb",
 ]
 QR_BATCH_TILE_BITS = 20
 
@@ -95,6 +95,7 @@ def _load():
         "qr_render_quantile_batched": ([P, i32, P, prm_p, i32, i32, i32, P, i64, i32, P, sz], i32),
         "qr_batch_schedule": ([P, i32, P, P, i64, P, P, sz], i32),
         "qr_render_quantile_batched_backward": ([P, i32, P, P, prm_p, i32, i32, i32, P, i64, i32, P, sz], i32),
+        "qr_sh_to_rgb": ([P, i64, i32, P, P, i32, cam_p, P, i32], i32),
         "qr_devoxelize": ([P, i64, i32, P, P, i64, i64, P, i32, P, P], i32),
         "qr_devoxelize_backward": ([P, i64, i32, P, P, i64, i64, i32, P, P, P], i32),
         "qr_autotune_batched": ([P, i32, P, prm_p, i32, i32, i32, ctypes.POINTER(ctypes.c_void_p), i32, i64,
@@ -445,6 +446,18 @@ def qr_autotune_batched(n_views, views_dev, params, K, dtype_code, dim, schedule
                                     _ptr(workspace) if workspace is not None else None, ws_bytes,
                                     times, ctypes.byref(bi), ctypes.byref(bw)))
     return bi.value, bw.value, [[times[i * nw + j] for j in range(nw)] for i in range(ns)]
+
+
+def qr_sh_to_rgb(means3d, sh, degree, camera, out, stream=None):
+    """means3d f32 [N,3]; sh f32 [N, S, 3] (S >= (degree+1)^2); out f32 [N, C]
+    (C >= 3): RGB in columns 0..2, zeros elsewhere."""
+    n = means3d.shape[0]
+    _need(means3d, 3 * n, F32, "means3d")
+    _need(sh, n * sh.shape[1] * 3, F32, "sh")
+    _need(out, n * out.shape[1], F32, "out")
+    cam = make_camera(camera)
+    _check(_LIB.qr_sh_to_rgb(_stream(stream), n, degree, _ptr(means3d), _ptr(sh), sh.shape[1],
+                             ctypes.byref(cam), _ptr(out), out.shape[1]))
 
 
 def qr_devoxelize(offsets, voxel_unique, unique_pred, reduce, out, argmax=None, stream=None):

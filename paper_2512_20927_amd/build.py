@@ -31,6 +31,7 @@ SOURCES = [
     "schedule.hip",
     "autotune.hip",
     "devoxelize.hip",
+    "sh.hip",
 ]
 
 # Packed FP32 instructions are switched off: float code is compiled to

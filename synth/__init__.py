@@ -17,5 +17,6 @@ from .scenes import (  # noqa: F401
     room_camera,
     make_fd_case,
     make_batched,
+    sh_coefficients,
     CONFIGS,
 )

@@ -205,3 +205,16 @@ CONFIGS = {
     "diff": dict(n=500_000, seed=3, dim=512, width=640, height=480, fx=577.0,
                  pose_seeds=[400], target_seed=4, fd_seed=5, K=8),
 }
+
+
+def sh_coefficients(n: int, degree: int = 3, seed: int = 0) -> np.ndarray:
+    """float32 [n, 16, 3] spherical-harmonic colour coefficients: the
+    constant term uniform in [-1.4, 1.4] per channel (base colours spread
+    over roughly [0.1, 0.9]), degree l >= 1 terms normal with standard
+    deviation 0.3 / l, columns past (degree+1)^2 zero."""
+    rng = np.random.default_rng(seed)
+    k = np.zeros((n, 16, 3), np.float32)
+    k[:, 0] = rng.uniform(-1.4, 1.4, (n, 3))
+    for l in range(1, degree + 1):
+        k[:, l * l:(l + 1) * (l + 1)] = rng.normal(0.0, 0.3 / l, (n, 2 * l + 1, 3))
+    return k

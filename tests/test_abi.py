@@ -199,6 +199,24 @@ def test_devoxelize_validation(L):
     assert rc == L.QR_ERR_INVALID_ARG  # max needs the argmax slots
 
 
+
+def test_sh_to_rgb_validation(L):
+    lib = L.lib()
+    d = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    cam = L.make_camera(type("C", (), dict(R_cw=[1, 0, 0, 0, 1, 0, 0, 0, 1], t=[0, 0, 3], fx=50.0,
+                                           fy=50.0, cx=32.0, cy=32.0, width=64, height=64))())
+    cp = ctypes.byref(cam)
+    sh = lambda n=10, deg=3, stride=16, c=cp, out_dim=16, m=d: lib.qr_sh_to_rgb(None, n, deg, m, d, stride, c, d,
+                                                                                 out_dim)
+    assert sh(n=-1) == L.QR_ERR_INVALID_ARG
+    assert sh(deg=4) == L.QR_ERR_UNSUPPORTED
+    assert sh(deg=-1) == L.QR_ERR_UNSUPPORTED
+    assert sh(stride=15) == L.QR_ERR_INVALID_ARG  # degree 3 needs 16 coefficients
+    assert sh(out_dim=2) == L.QR_ERR_INVALID_ARG
+    assert sh(c=None) == L.QR_ERR_INVALID_ARG
+    assert sh(m=None) == L.QR_ERR_INVALID_ARG
+    assert sh(n=0) == L.QR_OK  # nothing to do
+
 def test_views_front_validation(L):
     lib = L.lib()
     prm = L.make_params()
