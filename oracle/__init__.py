@@ -18,6 +18,8 @@ paper's definitions:
 * ``selection`` - the closed "interval" form of the quantile selection.
 * ``stratified`` - the Stratified-K variant (Appendix): per-ray thresholds
                   from the ray's transmittance statistics.
+* ``topk``      - the Top-K sampler the paper compares with (the K largest
+                  dense weights per ray, normalised by their sum).
 * ``devoxelize`` - per-Gaussian features as the max (or mean) of the
                   predictions of the voxels each Gaussian covers.
 * ``sh``        - view-dependent RGB from spherical-harmonic coefficients.
@@ -36,6 +38,7 @@ from .render import render_dense, render_quantile, quantile_thresholds  # noqa: 
 from .brute import brute_force_render  # noqa: F401
 from .selection import interval_selection  # noqa: F401
 from .sh import sh_basis, sh_to_rgb  # noqa: F401
+from .topk import render_topk  # noqa: F401
 from .devoxelize import devoxelize, devoxelize_backward  # noqa: F401
 from .stratified import render_stratified, stratified_thresholds, transmittance_stats  # noqa: F401
 from .backward import dense_backward, quantile_backward  # noqa: F401
