@@ -374,13 +374,13 @@ def run_room(args):
                                   "bytes_per_launch": round(bytes_bf)}}
         del states_bf, outs_bf
 
-    # side result: Stratified-K (Appendix) on the same binned poses, the
-    # batched launch alone (its front is the same as Q-Render's)
-    strat_side = None
-    if not args.renders_only:
+    # side results: Stratified-K (Appendix) and the Top-K sampler (the
+    # paper's speed comparison, Sec. 4.2) on the same binned poses, the
+    # batched launch alone (the front is the same as Q-Render's)
+    def side_render(selection):
         from paper_2512_20927_amd.batched import BatchedQuantile
         bq_s = BatchedQuantile(states[0].bq._views, K, D, L.QR_F32,
-                               qr.RenderParams(selection=L.QR_SELECT_STRATIFIED).c())
+                               qr.RenderParams(selection=selection).c())
         tuned_s, _ = autotune(bq_s, wg_per_cu=(0, 3, 8), use_cache=False)
         for _ in range(args.warmup):
             bq_s.render(tuned_s["schedule"], tuned_s["wg_per_cu"])
@@ -392,10 +392,14 @@ def run_room(args):
         ev[1].record()
         torch.cuda.synchronize()
         ms_s = ev[0].elapsed_time(ev[1]) / args.steps
-        strat_side = {"render_ms": round(ms_s, 4), "render_frames_per_s": round(n_views / (ms_s * 1e-3), 2),
-                      "quantile_render_frames_per_s": round(n_views / (k_seq * 1e-3), 2),
-                      "batched_launch": {k: tuned_s[k] for k in ("schedule", "wg_per_cu")}}
-        del bq_s
+        return {"render_ms": round(ms_s, 4), "render_frames_per_s": round(n_views / (ms_s * 1e-3), 2),
+                "quantile_render_frames_per_s": round(n_views / (k_seq * 1e-3), 2),
+                "batched_launch": {k: tuned_s[k] for k in ("schedule", "wg_per_cu")}}
+
+    strat_side = topk_side = None
+    if not args.renders_only:
+        strat_side = side_render(L.QR_SELECT_STRATIFIED)
+        topk_side = side_render(L.QR_SELECT_TOPK)
 
     cpu = None
     if args.cpu_budget > 0 and not args.renders_only:
@@ -439,6 +443,7 @@ def run_room(args):
         "cpu_baseline": cpu,
         "bf16_output": bf16_side,
         "stratified_k": strat_side,
+        "top_k": topk_side,
         "autotune_ms": {k: round(v, 3) for k, v in tune_ms.items()},
         "setup_s": round(t_setup, 1),
     }

@@ -70,10 +70,11 @@ typedef enum {
   QR_REDUCE_MEAN = 1
 } qr_reduce;
 
-/* Threshold rules of the Q-Render selection (qr_params.selection). */
+/* Selection rules of the Q-Render kernels (qr_params.selection). */
 typedef enum {
   QR_SELECT_QUANTILE = 0,   /* Algorithm 1 */
-  QR_SELECT_STRATIFIED = 1  /* Stratified-K (Appendix) */
+  QR_SELECT_STRATIFIED = 1, /* Stratified-K (Appendix) */
+  QR_SELECT_TOPK = 2        /* Top-K, the sampler compared with in Sec. 4.2 */
 } qr_selection;
 
 /* Pinhole camera, OpenCV axes (x right, y down, z forward). A world point X
@@ -118,7 +119,11 @@ typedef struct qr_params {
    * T_eps stop); then t_m = clip(mu + sigma Phi^-1(1 - m/(K+1)), 0, 1),
    * evaluated in double and rounded once to float, and Algorithm 1 runs with
    * these thresholds over the same Gaussians, ending at the dense stop or
-   * once all K are consumed). The backward passes
+   * once all K are consumed) or QR_SELECT_TOPK (2, the Top-K sampler that
+   * Sec. 4.2 and its complexity table compare with: among the Gaussians the
+   * dense blend composites, the K of largest dense weight T alpha' (equal
+   * weights: the earlier list position), blended with those weights and
+   * normalised by their sum; T_q reports 1 - that sum). The backward passes
    * support QR_SELECT_QUANTILE only. */
   int32_t selection;
 } qr_params;

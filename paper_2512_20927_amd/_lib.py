@@ -21,7 +21,7 @@ LIB_PATH = os.environ.get("QRENDER_LIB") or os.path.join(
 
 QR_OK, QR_ERR_INVALID_ARG, QR_ERR_UNSUPPORTED, QR_ERR_CAPACITY, QR_ERR_HIP = 0, -1, -2, -3, -4
 QR_F32, QR_BF16, QR_FP8_E4M3 = 0, 1, 2
-QR_SELECT_QUANTILE, QR_SELECT_STRATIFIED = 0, 1
+QR_SELECT_QUANTILE, QR_SELECT_STRATIFIED, QR_SELECT_TOPK = 0, 1, 2
 QR_REDUCE_MAX, QR_REDUCE_MEAN = 0, 1
 QR_TILE = 16
 QR_MAX_K = 32

@@ -117,6 +117,13 @@ struct PixelSel {
 // 1 and T after every Gaussian the dense blend composites, with its T_eps
 // stop; sums in double) and the thresholds are the ray's own; the second
 // pass examines the same Gaussians (it also ends at the dense stop).
+// MODE QR_SELECT_TOPK (the Top-K sampler the paper compares with): the
+// candidates are the Gaussians the dense blend composites (same T_eps stop),
+// each with its dense weight T alpha'; the K largest are kept (equal weights:
+// the earlier position), then put back in list order; 1 / (1 - T^Q) becomes
+// 1 / (sum of the kept weights) and T^Q reports 1 - that sum. A pixel is done
+// once its list is full and T alpha_max is no larger than the smallest kept
+// weight: no later weight can exceed it.
 template <int MODE, class WalkLds>
 __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi, int K, float pxc,
                                                   float pyc, bool inside, const qr_params& prm,
@@ -190,6 +197,8 @@ __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi
                                              : quantile_threshold(1, K);
   int* my_pos = s_sel_pos + tid * KP;
   float* my_w = s_sel_w + tid * KP;
+  float wmin = 0.f;  // Top-K: the worst kept entry (smallest weight, later position among equals)
+  int imin = 0;
 
   for (int batch = lo; batch < hi; batch += kTilePix) {
     if (__syncthreads_count(!done) == 0) break;
@@ -223,6 +232,41 @@ __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi
         const float alpha = gauss_alpha(rm[u], rc[u], pxc, pyc, amax);
         if (done || alpha < amin) continue;  // finished, or not on this pixel's ray
         const float T_test = T * (1.f - alpha);
+        if constexpr (MODE == QR_SELECT_TOPK) {
+          if (T_test < prm.T_eps) {  // the dense blend stops before this Gaussian
+            done = true;
+            continue;
+          }
+          const float w = T * alpha;
+          const int pos = batch + j + u;
+          if (ns < K) {
+            my_pos[ns] = pos;
+            my_w[ns] = w;
+            if (ns == 0 || w <= wmin) {
+              wmin = w;
+              imin = ns;
+            }
+            ++ns;
+          } else if (w > wmin) {
+            my_pos[imin] = pos;
+            my_w[imin] = w;
+            int pmin = my_pos[0];
+            wmin = my_w[0];
+            imin = 0;
+            for (int e = 1; e < K; ++e) {
+              const float we = my_w[e];
+              const int pe = my_pos[e];
+              if (we < wmin || (we == wmin && pe > pmin)) {
+                wmin = we;
+                imin = e;
+                pmin = pe;
+              }
+            }
+          }
+          T = T_test;
+          if (ns == K && T * amax <= wmin) done = true;
+          continue;
+        }
         if (MODE == QR_SELECT_STRATIFIED && T_test < prm.T_eps) {  // the sampled ray ends here
           done = true;
           continue;
@@ -240,6 +284,28 @@ __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi
         T = T_test;
       }
     }
+  }
+  if constexpr (MODE == QR_SELECT_TOPK) {
+    // back to list order (insertion sort of at most K entries), weight sum
+    for (int a = 1; a < ns; ++a) {
+      const int p = my_pos[a];
+      const float w = my_w[a];
+      int b = a - 1;
+      while (b >= 0 && my_pos[b] > p) {
+        my_pos[b + 1] = my_pos[b];
+        my_w[b + 1] = my_w[b];
+        --b;
+      }
+      my_pos[b + 1] = p;
+      my_w[b + 1] = w;
+    }
+    float sum = 0.f;
+    for (int a = 0; a < ns; ++a) sum += my_w[a];
+    TQ = 1.f - sum;
+    L.ns[tid] = inside ? ns : -1;
+    L.inv[tid] = ns > 0 ? 1.f / sum : 0.f;
+    wave_lds_sync();
+    return PixelSel{ns, TQ};
   }
   L.ns[tid] = inside ? ns : -1;
   L.inv[tid] = ns > 0 ? 1.f / (1.f - TQ) : 0.f;

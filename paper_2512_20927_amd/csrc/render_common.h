@@ -123,7 +123,8 @@ inline int validate_render(const char* name, int32_t width, int32_t height, cons
   if (!(prm->T_eps >= 0.f)) return fail(QR_ERR_INVALID_ARG, "%s: T_eps must be >= 0", name);
   if (prm->out_dtype != QR_F32 && prm->out_dtype != QR_BF16)
     return fail(QR_ERR_UNSUPPORTED, "%s: unknown output dtype %d", name, prm->out_dtype);
-  if (prm->selection != QR_SELECT_QUANTILE && prm->selection != QR_SELECT_STRATIFIED)
+  if (prm->selection != QR_SELECT_QUANTILE && prm->selection != QR_SELECT_STRATIFIED &&
+      prm->selection != QR_SELECT_TOPK)
     return fail(QR_ERR_UNSUPPORTED, "%s: unknown selection rule %d", name, prm->selection);
   if (!tile_offsets || !sorted_gid || !means2d || !conic_opacity || !features || !out)
     return fail(QR_ERR_INVALID_ARG, "%s: null array pointer", name);

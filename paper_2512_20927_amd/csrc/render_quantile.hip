@@ -328,7 +328,10 @@ using namespace qr;
   }
 #define QR_DISPATCH(dt, ot, sm)                                                   \
   do {                                                                            \
-    if ((sm) == QR_SELECT_STRATIFIED) {                                           \
+    if ((sm) == QR_SELECT_TOPK) {                                                 \
+      if ((ot) == QR_BF16) { QR_DISPATCH_DT(dt, QR_BF16, QR_SELECT_TOPK) }       \
+      else { QR_DISPATCH_DT(dt, QR_F32, QR_SELECT_TOPK) }                        \
+    } else if ((sm) == QR_SELECT_STRATIFIED) {                                    \
       if ((ot) == QR_BF16) { QR_DISPATCH_DT(dt, QR_BF16, QR_SELECT_STRATIFIED) } \
       else { QR_DISPATCH_DT(dt, QR_F32, QR_SELECT_STRATIFIED) }                  \
     } else {                                                                      \
@@ -392,7 +395,8 @@ extern "C" int qr_render_quantile_batched(void* stream, int32_t n_views, const q
     return fail(QR_ERR_INVALID_ARG, "qr_render_quantile_batched: need 0 < alpha_min <= alpha_max < 1");
   if (prm->out_dtype != QR_F32 && prm->out_dtype != QR_BF16)
     return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile_batched: unknown output dtype %d", prm->out_dtype);
-  if (prm->selection != QR_SELECT_QUANTILE && prm->selection != QR_SELECT_STRATIFIED)
+  if (prm->selection != QR_SELECT_QUANTILE && prm->selection != QR_SELECT_STRATIFIED &&
+      prm->selection != QR_SELECT_TOPK)
     return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile_batched: unknown selection rule %d", prm->selection);
   if (n_items == 0) return QR_OK;
   hipStream_t s = as_stream(stream);

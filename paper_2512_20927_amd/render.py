@@ -25,7 +25,7 @@ class RenderParams:
     dilation: float = 0.3
     guard: float = 1.3
     out_dtype: int = L.QR_F32  # Q-Render feature maps: L.QR_F32 or L.QR_BF16
-    selection: int = L.QR_SELECT_QUANTILE  # or L.QR_SELECT_STRATIFIED (Stratified-K)
+    selection: int = L.QR_SELECT_QUANTILE  # or QR_SELECT_STRATIFIED (Stratified-K), QR_SELECT_TOPK
 
     def c(self) -> L.qr_params:
         return L.make_params(self.alpha_min, self.alpha_max, self.T_eps, self.dilation, self.guard,

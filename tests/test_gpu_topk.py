@@ -1,0 +1,113 @@
+"""Top-K (qr_params.selection = QR_SELECT_TOPK) on the GPU against the FP64
+oracle's render_topk, fed the GPU's projected float32 records and bins: on
+pixels whose every decision (alpha' vs alpha_min, T vs T_eps, the K-th against
+the (K+1)-th weight) is further than the decision window from its boundary,
+identical selections in list order, their weights, T_q and feature maps
+within the float32 tolerance; the batched launch reproduces the single-view
+kernel bit for bit; the backward passes reject the rule."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.parity_util import DECISION_WINDOW, FP32_TOL, pixel_rel_err, proj_for_oracle
+from tests.test_gpu_batched import _make_views
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_20927_amd as qr
+    return qr
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _case(qr, sc, cam, K):
+    from paper_2512_20927_amd import _lib as L
+    W, H = cam.width, cam.height
+    pr = qr.project(_t(sc.means), _t(sc.scales), _t(sc.quats), _t(sc.opacity), cam)
+    bins = qr.bin_sort(pr, W, H)
+    feats = _t(sc.features)
+    prm = qr.RenderParams(selection=L.QR_SELECT_TOPK)
+    got = qr.render_quantile(pr, bins, feats, W, H, K, params=prm, debug=True)
+    torch.cuda.synchronize()
+    P = int(bins.total_pairs.item())
+    host = dict(means2d=pr.means2d.cpu().numpy(), conic_opacity=pr.conic_opacity.cpu().numpy())
+    gids = bins.sorted_gid.cpu().numpy()[:P].astype(np.int64)
+    offs = bins.tile_offsets.cpu().numpy().astype(np.int64)
+    ref = oracle.render_topk(proj_for_oracle(host), gids, offs, sc.features.astype(np.float64), W, H, K)
+    return got, ref
+
+
+def _check(got, ref, K):
+    clear = ref["margin"] > DECISION_WINDOW
+    assert clear.mean() > 0.8, clear.mean()
+    ns = got["n_sel"].cpu().numpy()
+    np.testing.assert_array_equal(ns[clear], ref["n_sel"][clear])
+    np.testing.assert_array_equal(got["sel_gid"].cpu().numpy()[clear], ref["sel_gid"][clear])
+    np.testing.assert_allclose(got["sel_w"].cpu().numpy()[..., :K][clear], ref["sel_w"][clear],
+                               rtol=1e-4, atol=1e-7)
+    np.testing.assert_allclose(got["T_q"].cpu().numpy()[clear], ref["T_q"][clear], rtol=1e-4, atol=1e-5)
+    err = pixel_rel_err(got["out"].cpu().numpy()[clear], ref["out"][clear])
+    assert err.max() <= FP32_TOL, err.max()
+    assert (ns <= K).all()
+    # some rays hold more candidates than K (the ranking is exercised)
+    assert (ref["n_cand"][clear] > K).mean() > 0.05
+
+
+@pytest.mark.parametrize("K", [1, 8, 32])
+def test_topk_matches_oracle_ragged(qr, K):
+    sc = synth.make_tiny(3, n=3000, dim=32)
+    cam = synth.tiny_camera(100)
+    cam.height, cam.cy = 75, 37.5
+    got, ref = _case(qr, sc, cam, K)
+    _check(got, ref, K)
+
+
+def test_topk_room_tiles(qr):
+    """Room-generator scene (30k Gaussians), 160x120: realistic ray lengths."""
+    sc = synth.make_room(30_000, 9, dim=16)
+    cam = synth.room_camera(130, 160, 120, 144.0)
+    got, ref = _case(qr, sc, cam, 8)
+    _check(got, ref, 8)
+
+
+def test_topk_batched_matches_single_view(qr):
+    from paper_2512_20927_amd import _lib as L
+    from paper_2512_20927_amd.batched import BatchedQuantile
+    views, _ = _make_views(qr, "f32")
+    prm = qr.RenderParams(selection=L.QR_SELECT_TOPK)
+    single = []
+    for v in views:
+        single.append(qr.render_quantile(v["_pr"], v["_bins"], v["features"], v["width"], v["height"], 8,
+                                         params=prm))
+    bq = BatchedQuantile(views, 8, 32, L.QR_F32, prm.c())
+    for w in (0, 3):
+        for v in views:
+            v["out"].fill_(float("nan"))
+        bq.render("heavy", w)
+        torch.cuda.synchronize()
+        for v, ref in zip(views, single):
+            assert torch.equal(v["out"], ref["out"]) and torch.equal(v["n_sel"], ref["n_sel"]), w
+
+
+def test_backward_rejects_topk(qr):
+    from paper_2512_20927_amd import _lib as L
+    sc = synth.make_tiny(1, n=500, dim=16)
+    cam = synth.tiny_camera(32)
+    pr = qr.project(_t(sc.means), _t(sc.scales), _t(sc.quats), _t(sc.opacity), cam)
+    bins = qr.bin_sort(pr, 32, 32)
+    g = torch.zeros(32, 32, 16, device="cuda")
+    gf = torch.zeros(500, 16, device="cuda")
+    with pytest.raises(L.QRError):
+        L.qr_render_quantile_backward(32, 32, L.make_params(selection=L.QR_SELECT_TOPK), 8,
+                                      bins.tile_offsets, bins.sorted_gid, pr.means2d, pr.conic_opacity,
+                                      _t(sc.features), None, g, gf, None, None)
