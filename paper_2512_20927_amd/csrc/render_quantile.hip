@@ -115,6 +115,62 @@ __device__ __forceinline__ void gather_group_merged(const GView& v, const Quanti
   }
 }
 
+// Gather-blend of all sixteen merged groups of a wave at once, for narrow
+// rows (dim <= 128): lpg lanes per group (the power of two >= dim / 4, one
+// float4 column each), so 64 / lpg groups are blended side by side, and all
+// kUCap row loads of a lane are requested before the first is used (slots
+// past a group's distinct count load a row of the group again and are not
+// accumulated). One memory round trip per round instead of one per group.
+// Groups with more than kUCap distinct selections are skipped here.
+template <int DT, int OT>
+__device__ __forceinline__ void gather_groups_narrow(const GView& v, const QuantileLds& L, int wave,
+                                                     int tx, int ty, int lane, int dim) {
+  const int dim4 = dim >> 2;
+  const int lpg_log = dim4 <= 4 ? 2 : dim4 <= 8 ? 3 : dim4 <= 16 ? 4 : 5;
+  const int gpr = 64 >> lpg_log;  // groups per round
+  const int c = lane & ((1 << lpg_log) - 1);
+  const int cl = min(c, dim4 - 1);  // in-bounds column to load
+  constexpr int kWaveGroups = kGroups / 4;
+  for (int r0 = 0; r0 < kWaveGroups; r0 += gpr) {
+    const int grp = wave * kWaveGroups + r0 + (lane >> lpg_log);
+    const int nu = L.unum[grp];
+    float4 a[kPG];
+#pragma unroll
+    for (int q = 0; q < kPG; ++q) a[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (nu > 0) {
+      const int* ug = &L.ugid[grp * kUCap];
+      float4 f[kUCap];
+#pragma unroll
+      for (int e = 0; e < kUCap; ++e)
+        f[e] = load_feat4_global<DT>(v.feats, v.scale, ug[min(e, nu - 1)], dim, 4 * cl);
+#pragma unroll
+      for (int e = 0; e < kUCap; ++e) {
+        if (e < nu) {
+          const float4 w = L.uw[grp * kUCap + e];
+          const float ws[kPG] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+          for (int q = 0; q < kPG; ++q) {
+            a[q].x += ws[q] * f[e].x;
+            a[q].y += ws[q] * f[e].y;
+            a[q].z += ws[q] * f[e].z;
+            a[q].w += ws[q] * f[e].w;
+          }
+        }
+      }
+    }
+    if (nu >= 0 && c < dim4) {
+      const int p0 = grp * kPG;
+#pragma unroll
+      for (int q = 0; q < kPG; ++q) {
+        const int p = p0 + q;
+        if (L.ns[p] < 0) continue;  // outside the image
+        const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
+        store_out4<OT>(v.out, static_cast<int64_t>(gy) * v.W + gx, dim, c, a[q]);
+      }
+    }
+  }
+}
+
 // Gather-blend of a group with more than kUCap distinct selections: pixel
 // by pixel, each selection's row loaded for its own pixel.
 template <int DT, int OT>
@@ -203,13 +259,15 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
   const int lane = tid & 63;
   const int wave = tid >> 6;
   constexpr int kWaveGroups = kGroups / 4;
+  const bool narrow = dim <= 128;
+  if (narrow) gather_groups_narrow<DT, OT>(v, L, wave, tx, ty, lane, dim);
   for (int gl = 0; gl < kWaveGroups; ++gl) {
     const int grp = wave * kWaveGroups + gl;
     const int nu = __builtin_amdgcn_readfirstlane(L.unum[grp]);
-    if (nu >= 0)
-      gather_group_merged<DT, OT>(v, L, grp, nu, tx, ty, lane, dim);
-    else  // more distinct selections than kUCap (rare)
+    if (nu < 0)  // more distinct selections than kUCap (rare)
       gather_group_per_pixel<DT, OT>(v, L, s_sel_pos, s_sel_w, KP, grp, tx, ty, lane, dim);
+    else if (!narrow)
+      gather_group_merged<DT, OT>(v, L, grp, nu, tx, ty, lane, dim);
   }
   // Per-pixel outputs last: a load issued after a store waits for it, so no
   // store precedes the loads of the merge and the gather.

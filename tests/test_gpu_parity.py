@@ -188,6 +188,20 @@ def test_render_parity_tiny(qr):
     check_all(res, ors, 64, 64)
 
 
+@pytest.mark.parametrize("dim,K", [(16, 8), (16, 32), (48, 8), (128, 8), (128, 32), (144, 8)])
+def test_render_parity_feature_widths(qr, dim, K):
+    """Rows of at most 128 features take the gather that blends all groups of
+    a wave side by side (4, 16 or 32 lanes per group); 144 takes the
+    column-pass gather with a partial pass. K = 32 puts groups past the
+    distinct-selection capacity onto the per-pixel path."""
+    sc = synth.make_tiny(5, n=3000, dim=dim)
+    cam = synth.tiny_camera(100)
+    cam.height, cam.cy = 75, 37.5
+    res = gpu_pipeline(qr, sc, cam, K, dense=False)
+    ors = oracle_renders(res, sc.features.astype(np.float64), 100, 75, K, dense=False)
+    check_all(res, ors, 100, 75, dense=False)
+
+
 @pytest.mark.parametrize("K", [1, 4, 32])
 def test_render_parity_ragged_image(qr, K):
     sc = synth.make_tiny(3, n=3000, dim=32)
