@@ -452,6 +452,12 @@ def qr_sh_to_rgb(means3d, sh, degree, camera, out, stream=None):
     """means3d f32 [N,3]; sh f32 [N, S, 3] (S >= (degree+1)^2); out f32 [N, C]
     (C >= 3): RGB in columns 0..2, zeros elsewhere."""
     n = means3d.shape[0]
+    if means3d.dim() != 2 or means3d.shape[1] != 3:
+        raise ValueError("means3d must be [N, 3]")
+    if sh.dim() != 3 or sh.shape[0] != n or sh.shape[2] != 3:
+        raise ValueError("sh must be [N, S, 3] with N = %d" % n)
+    if out.dim() != 2 or out.shape[0] != n:
+        raise ValueError("out must be [N, C] with N = %d" % n)
     _need(means3d, 3 * n, F32, "means3d")
     _need(sh, n * sh.shape[1] * 3, F32, "sh")
     _need(out, n * out.shape[1], F32, "out")
