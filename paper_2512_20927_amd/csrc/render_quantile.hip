@@ -171,6 +171,67 @@ __device__ __forceinline__ void gather_groups_narrow(const GView& v, const Quant
   }
 }
 
+// The groups that gather_groups_narrow skipped (more than kUCap distinct
+// selections), with the same lane layout: pixel by pixel, each pixel's
+// selections taken eight at a time (their ids, then their rows, each batch
+// requested together), all such groups of a round side by side.
+template <int DT, int OT>
+__device__ __forceinline__ void gather_groups_narrow_overflow(const GView& v, const QuantileLds& L,
+                                                              const int* __restrict__ s_sel_pos,
+                                                              const float* __restrict__ s_sel_w,
+                                                              int KP, int K, int wave, int tx, int ty,
+                                                              int lane, int dim) {
+  constexpr int kChunk = 8;
+  const int dim4 = dim >> 2;
+  const int lpg_log = dim4 <= 4 ? 2 : dim4 <= 8 ? 3 : dim4 <= 16 ? 4 : 5;
+  const int gpr = 64 >> lpg_log;
+  const int c = lane & ((1 << lpg_log) - 1);
+  const int cl = min(c, dim4 - 1);
+  constexpr int kWaveGroups = kGroups / 4;
+  for (int r0 = 0; r0 < kWaveGroups; r0 += gpr) {
+    const int grp = wave * kWaveGroups + r0 + (lane >> lpg_log);
+    const bool mine = L.unum[grp] < 0;
+    if (!__any(mine)) continue;
+#pragma unroll 1
+    for (int q = 0; q < kPG; ++q) {
+      const int p = grp * kPG + q;
+      const int n = mine ? L.ns[p] : -1;  // -1: not this path's pixel, or outside the image
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int j0 = 0; j0 < K; j0 += kChunk) {
+        if (!__any(n > j0)) break;
+        if (n > j0) {
+          int g[kChunk];
+          float w[kChunk];
+#pragma unroll
+          for (int jj = 0; jj < kChunk; ++jj) {
+            const int j = min(j0 + jj, n - 1);
+            g[jj] = static_cast<int>(v.sorted_gid[s_sel_pos[p * KP + j]]);
+            w[jj] = s_sel_w[p * KP + j];
+          }
+          float4 f[kChunk];
+#pragma unroll
+          for (int jj = 0; jj < kChunk; ++jj) f[jj] = load_feat4_global<DT>(v.feats, v.scale, g[jj], dim, 4 * cl);
+#pragma unroll
+          for (int jj = 0; jj < kChunk; ++jj) {
+            if (j0 + jj < n) {
+              a.x += w[jj] * f[jj].x;
+              a.y += w[jj] * f[jj].y;
+              a.z += w[jj] * f[jj].z;
+              a.w += w[jj] * f[jj].w;
+            }
+          }
+        }
+      }
+      if (n >= 0 && c < dim4) {
+        const int gx = tx * kTile + (p % kTile), gy = ty * kTile + (p / kTile);
+        const float inv = L.inv[p];
+        store_out4<OT>(v.out, static_cast<int64_t>(gy) * v.W + gx, dim, c,
+                       make_float4(a.x * inv, a.y * inv, a.z * inv, a.w * inv));
+      }
+    }
+  }
+}
+
 // Gather-blend of a group with more than kUCap distinct selections: pixel
 // by pixel, each selection's row loaded for its own pixel.
 template <int DT, int OT>
@@ -259,15 +320,18 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
   const int lane = tid & 63;
   const int wave = tid >> 6;
   constexpr int kWaveGroups = kGroups / 4;
-  const bool narrow = dim <= 128;
-  if (narrow) gather_groups_narrow<DT, OT>(v, L, wave, tx, ty, lane, dim);
-  for (int gl = 0; gl < kWaveGroups; ++gl) {
-    const int grp = wave * kWaveGroups + gl;
-    const int nu = __builtin_amdgcn_readfirstlane(L.unum[grp]);
-    if (nu < 0)  // more distinct selections than kUCap (rare)
-      gather_group_per_pixel<DT, OT>(v, L, s_sel_pos, s_sel_w, KP, grp, tx, ty, lane, dim);
-    else if (!narrow)
-      gather_group_merged<DT, OT>(v, L, grp, nu, tx, ty, lane, dim);
+  if (dim <= 128) {
+    gather_groups_narrow<DT, OT>(v, L, wave, tx, ty, lane, dim);
+    gather_groups_narrow_overflow<DT, OT>(v, L, s_sel_pos, s_sel_w, KP, K, wave, tx, ty, lane, dim);
+  } else {
+    for (int gl = 0; gl < kWaveGroups; ++gl) {
+      const int grp = wave * kWaveGroups + gl;
+      const int nu = __builtin_amdgcn_readfirstlane(L.unum[grp]);
+      if (nu >= 0)
+        gather_group_merged<DT, OT>(v, L, grp, nu, tx, ty, lane, dim);
+      else  // more distinct selections than kUCap (rare)
+        gather_group_per_pixel<DT, OT>(v, L, s_sel_pos, s_sel_w, KP, grp, tx, ty, lane, dim);
+    }
   }
   // Per-pixel outputs last: a load issued after a store waits for it, so no
   // store precedes the loads of the merge and the gather.

@@ -72,6 +72,34 @@ def test_topk_matches_oracle_ragged(qr, K):
     _check(got, ref, K)
 
 
+@pytest.mark.parametrize("storage", ["bf16", "fp8"])
+def test_topk_quantized_storage_bf16_maps(qr, storage):
+    """bf16 / e4m3 feature storage (decoded in the load path) and bfloat16
+    output maps: against the oracle on the decoded features, the map within
+    one bfloat16 rounding of the float32 result."""
+    from paper_2512_20927_amd import _lib as L
+    from tests.test_gpu_parity import decoded_features
+    sc = synth.make_tiny(4, n=3000, dim=48)
+    cam = synth.tiny_camera(80)
+    W, H, K = 80, 80, 8
+    pr = qr.project(_t(sc.means), _t(sc.scales), _t(sc.quats), _t(sc.opacity), cam)
+    bins = qr.bin_sort(pr, W, H)
+    feats, scale = qr.quantize(_t(sc.features), storage)
+    prm = qr.RenderParams(selection=L.QR_SELECT_TOPK, out_dtype=L.QR_BF16)
+    got = qr.render_quantile(pr, bins, feats, W, H, K, feature_scale=scale, params=prm)
+    torch.cuda.synchronize()
+    P = int(bins.total_pairs.item())
+    host = dict(means2d=pr.means2d.cpu().numpy(), conic_opacity=pr.conic_opacity.cpu().numpy())
+    gids = bins.sorted_gid.cpu().numpy()[:P].astype(np.int64)
+    offs = bins.tile_offsets.cpu().numpy().astype(np.int64)
+    dec = decoded_features(qr, sc, dict(feats=feats, scale=scale), storage)
+    ref = oracle.render_topk(proj_for_oracle(host), gids, offs, dec, W, H, K)
+    clear = ref["margin"] > DECISION_WINDOW
+    assert got["out"].dtype == torch.bfloat16 and clear.mean() > 0.8
+    err = pixel_rel_err(got["out"].float().cpu().numpy()[clear], ref["out"][clear])
+    assert err.max() <= 2 ** -8, err.max()  # bfloat16 rounding of each element
+
+
 def test_topk_room_tiles(qr):
     """Room-generator scene (30k Gaussians), 160x120: realistic ray lengths."""
     sc = synth.make_room(30_000, 9, dim=16)
