@@ -188,12 +188,12 @@ def test_render_parity_tiny(qr):
     check_all(res, ors, 64, 64)
 
 
-@pytest.mark.parametrize("dim,K", [(16, 8), (16, 32), (48, 8), (128, 8), (128, 32), (144, 8)])
+@pytest.mark.parametrize("dim,K", [(16, 8), (16, 32), (48, 8), (128, 8), (128, 32), (144, 8), (1040, 4)])
 def test_render_parity_feature_widths(qr, dim, K):
     """Rows of at most 128 features take the gather that blends all groups of
     a wave side by side (4, 16 or 32 lanes per group); 144 takes the
-    column-pass gather with a partial pass. K = 32 puts groups past the
-    distinct-selection capacity onto the per-pixel path."""
+    column-pass gather with a partial pass, 1040 three passes. K = 32 puts
+    groups past the distinct-selection capacity onto the per-pixel path."""
     sc = synth.make_tiny(5, n=3000, dim=dim)
     cam = synth.tiny_camera(100)
     cam.height, cam.cy = 75, 37.5

@@ -63,9 +63,10 @@ def _check(got, ref, K):
     assert (ref["n_cand"][clear] > K).mean() > 0.05
 
 
-@pytest.mark.parametrize("K", [1, 8, 32])
-def test_topk_matches_oracle_ragged(qr, K):
-    sc = synth.make_tiny(3, n=3000, dim=32)
+@pytest.mark.parametrize("K,dim", [(1, 32), (8, 32), (32, 32), (8, 144)])
+def test_topk_matches_oracle_ragged(qr, K, dim):
+    """dim 32 takes the narrow-row gather, 144 the column-pass gather."""
+    sc = synth.make_tiny(3, n=3000, dim=dim)
     cam = synth.tiny_camera(100)
     cam.height, cam.cy = 75, 37.5
     got, ref = _case(qr, sc, cam, K)
