@@ -188,7 +188,7 @@ def test_render_parity_tiny(qr):
     check_all(res, ors, 64, 64)
 
 
-@pytest.mark.parametrize("dim,K", [(16, 8), (16, 32), (48, 8), (128, 8), (128, 32), (144, 8), (1040, 4)])
+@pytest.mark.parametrize("dim,K", [(16, 8), (16, 32), (48, 8), (128, 8), (128, 32), (144, 8), (144, 32), (1040, 4)])
 def test_render_parity_feature_widths(qr, dim, K):
     """Rows of at most 128 features take the gather that blends all groups of
     a wave side by side (4, 16 or 32 lanes per group); 144 takes the
