@@ -107,14 +107,16 @@ class BatchState:
 
 class RgbState(BatchState):
     """BatchState whose feature table is per pose: the view-dependent colours
-    of degree-3 spherical harmonics, evaluated for every pose in the front
-    (columns 0..2 of a 16-wide table, the rest zero)."""
+    of degree-3 spherical harmonics, evaluated for every pose in the front by
+    one multi-camera launch (columns 0..2 of a 16-wide table, the rest
+    zero)."""
 
     def __init__(self, qr, L, scene_t, sh, cams, W, H, capacity, outs, aux_f, aux_i, K):
         import torch
         n = scene_t["means"].shape[0]
         self.sh, self.cams_py = sh, cams
-        self.rgb = [torch.empty(n, 16, device="cuda") for _ in cams]
+        self.rgb_all = torch.empty(len(cams), n, 16, device="cuda")
+        self.rgb = [self.rgb_all[v] for v in range(len(cams))]
         super().__init__(qr, L, scene_t, cams, W, H, capacity, outs, aux_f, aux_i, K, 16)
 
     def make_bq(self, K):
@@ -127,8 +129,7 @@ class RgbState(BatchState):
         return BatchedQuantile(views, K, 16, self.L.QR_F32, self.prm)
 
     def front(self):
-        for v, cam in enumerate(self.cams_py):
-            self.L.qr_sh_to_rgb(self.s["means"], self.sh, 3, cam, self.rgb[v])
+        self.L.qr_sh_to_rgb_views(self.s["means"], self.sh, 3, self.cams_py, self.rgb_all)
         super().front()
 
     def render_dense(self):

@@ -442,6 +442,20 @@ int qr_sh_to_rgb(void* stream, int64_t n, int32_t degree, const float* means3d, 
                  int32_t coef_stride, const qr_camera* cam, float* out, int32_t out_dim);
 
 /*
+ * qr_sh_to_rgb_views - qr_sh_to_rgb for a batch of n_views cameras (the same
+ * colour model, Appendix "Rendering RGB"), each Gaussian's coefficients read
+ * once for every camera of a launch (one launch per 32 cameras). cams: HOST
+ * array of n_views cameras (their centres are copied into the launch
+ * arguments; the call keeps no pointer). out: device f32[n_views, n,
+ * out_dim]; view v's table starts at out + v*n*out_dim, out_dim a positive
+ * multiple of 4 (16-byte rows). Errors: as qr_sh_to_rgb, QR_ERR_INVALID_ARG
+ * for n_views <= 0, QR_ERR_UNSUPPORTED for out_dim not a multiple of 4.
+ */
+int qr_sh_to_rgb_views(void* stream, int64_t n, int32_t degree, const float* means3d,
+                       const float* sh, int32_t coef_stride, const qr_camera* cams,
+                       int32_t n_views, float* out, int32_t out_dim);
+
+/*
  * qr_devoxelize - per-Gaussian features from voxel predictions (the step that
  * produces the feature table the renderer reads; Appendix, de-voxelisation):
  * out[g, c] = reduce over slots m in [offsets[g], offsets[g+1]) of

@@ -32,7 +32,7 @@ EXPORTED = [
     "qr_render_dense_backward", "qr_render_quantile_backward", "qr_quantize_features",
     "qr_render_quantile_batched", "qr_batch_schedule", "qr_project_views", "qr_bin_sort_views",
     "qr_render_quantile_batched_backward", "qr_autotune_batched", "qr_devoxelize",
-    "qr_devoxelize_backward", "qr_sh_to_rgb",
+    "qr_devoxelize_backward", "qr_sh_to_rgb", "qr_sh_to_rgb_views",
 ]
 QR_BATCH_TILE_BITS = 20
 
@@ -96,6 +96,7 @@ def _load():
         "qr_batch_schedule": ([P, i32, P, P, i64, P, P, sz], i32),
         "qr_render_quantile_batched_backward": ([P, i32, P, P, prm_p, i32, i32, i32, P, i64, i32, P, sz], i32),
         "qr_sh_to_rgb": ([P, i64, i32, P, P, i32, cam_p, P, i32], i32),
+        "qr_sh_to_rgb_views": ([P, i64, i32, P, P, i32, cam_p, i32, P, i32], i32),
         "qr_devoxelize": ([P, i64, i32, P, P, i64, i64, P, i32, P, P], i32),
         "qr_devoxelize_backward": ([P, i64, i32, P, P, i64, i64, i32, P, P, P], i32),
         "qr_autotune_batched": ([P, i32, P, prm_p, i32, i32, i32, ctypes.POINTER(ctypes.c_void_p), i32, i64,
@@ -464,6 +465,26 @@ def qr_sh_to_rgb(means3d, sh, degree, camera, out, stream=None):
     cam = make_camera(camera)
     _check(_LIB.qr_sh_to_rgb(_stream(stream), n, degree, _ptr(means3d), _ptr(sh), sh.shape[1],
                              ctypes.byref(cam), _ptr(out), out.shape[1]))
+
+
+def qr_sh_to_rgb_views(means3d, sh, degree, cameras, out, stream=None):
+    """qr_sh_to_rgb for a list of cameras: out f32 [V, N, C] (C >= 3), view
+    v's colour table in out[v]."""
+    n = means3d.shape[0]
+    if means3d.dim() != 2 or means3d.shape[1] != 3:
+        raise ValueError("means3d must be [N, 3]")
+    if sh.dim() != 3 or sh.shape[0] != n or sh.shape[2] != 3:
+        raise ValueError("sh must be [N, S, 3] with N = %d" % n)
+    if out.dim() != 3 or out.shape[0] != len(cameras) or out.shape[1] != n:
+        raise ValueError("out must be [V, N, C] with V = %d, N = %d" % (len(cameras), n))
+    _need(means3d, 3 * n, F32, "means3d")
+    _need(sh, n * sh.shape[1] * 3, F32, "sh")
+    _need(out, len(cameras) * n * out.shape[2], F32, "out")
+    if out.data_ptr() % 16:
+        raise ValueError("out must be 16-byte aligned")
+    cams = make_cameras(cameras)
+    _check(_LIB.qr_sh_to_rgb_views(_stream(stream), n, degree, _ptr(means3d), _ptr(sh), sh.shape[1],
+                                   cams, len(cameras), _ptr(out), out.shape[2]))
 
 
 def qr_devoxelize(offsets, voxel_unique, unique_pred, reduce, out, argmax=None, stream=None):

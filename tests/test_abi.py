@@ -216,6 +216,14 @@ def test_sh_to_rgb_validation(L):
     assert sh(c=None) == L.QR_ERR_INVALID_ARG
     assert sh(m=None) == L.QR_ERR_INVALID_ARG
     assert sh(n=0) == L.QR_OK  # nothing to do
+    cams = L.make_cameras([cam, cam])
+    shv = lambda n=10, nv=2, c=cams: lib.qr_sh_to_rgb_views(None, n, 3, d, d, 16, c, nv, d, 16)
+    assert shv(nv=0) == L.QR_ERR_INVALID_ARG
+    assert shv(c=None) == L.QR_ERR_INVALID_ARG
+    assert shv(n=-1) == L.QR_ERR_INVALID_ARG
+    assert lib.qr_sh_to_rgb_views(None, 10, 5, d, d, 16, cams, 2, d, 16) == L.QR_ERR_UNSUPPORTED
+    assert lib.qr_sh_to_rgb_views(None, 10, 3, d, d, 16, cams, 2, d, 6) == L.QR_ERR_UNSUPPORTED
+    assert shv(n=0) == L.QR_OK
 
 def test_views_front_validation(L):
     lib = L.lib()
