@@ -4,9 +4,10 @@
 // below at 0, d the unit vector from the camera centre to the mean (zero for
 // a mean at the centre); Y_lm the real orthonormal harmonics carrying the
 // Condon-Shortley phase (-1)^m (the sign convention of 3D-GS coefficients),
-// m = -l .. l, coefficient index l^2 + l + m. One thread per Gaussian; the colour goes to
-// columns 0..2 of an out_dim-wide feature row (the rest zero) so that the
-// renderers take it as a feature table.
+// m = -l .. l, coefficient index l^2 + l + m. The colour goes to columns
+// 0..2 of an out_dim-wide feature row (the rest zero) so that the renderers
+// take it as a feature table: one thread per Gaussian for one camera, or
+// out_dim / 4 lanes per Gaussian for a batch of cameras.
 #include "common.h"
 #include "render_common.h"
 
