@@ -70,23 +70,26 @@ def test_rgb_render_parity(qr):
                        max_unexplained=1e-3)
 
 
-@pytest.mark.parametrize("n_views", [3, 37])  # 37: two launches of at most 32 cameras
-def test_sh_colours_views_match_per_view(qr, n_views):
+@pytest.mark.parametrize("n_views,degree,out_dim,stride", [(3, 3, 16, 16), (37, 3, 16, 16), (3, 0, 4, 1),
+                                                           (5, 2, 20, 9)])
+def test_sh_colours_views_match_per_view(qr, n_views, degree, out_dim, stride):
     """The batched colour kernel against the single-camera one (same
-    arithmetic, coefficients read once) and the oracle."""
+    arithmetic, coefficients read once) and the oracle; 37 cameras take two
+    launches of at most 32; out_dim / 4 = 1, 4 and 5 lanes per Gaussian;
+    coefficient rows exactly (degree + 1)^2 long."""
     from paper_2512_20927_amd import _lib as L
-    rng = np.random.default_rng(11)
+    rng = np.random.default_rng(11 + degree)
     n = 3001
     mu = rng.uniform(-1, 1, (n, 3)).astype(np.float32)
-    sh = (rng.standard_normal((n, 16, 3)) * 0.4).astype(np.float32)
+    sh = (rng.standard_normal((n, stride, 3)) * 0.4).astype(np.float32)
     cams = [synth.room_camera(900 + v, 64, 48, 50.0) for v in range(n_views)]
-    out = torch.full((n_views, n, 16), float("nan"), device="cuda")
-    L.qr_sh_to_rgb_views(_t(mu), _t(sh), 3, cams, out)
-    one = torch.empty(n, 16, device="cuda")
+    out = torch.full((n_views, n, out_dim), float("nan"), device="cuda")
+    L.qr_sh_to_rgb_views(_t(mu), _t(sh), degree, cams, out)
+    one = torch.empty(n, out_dim, device="cuda")
     for v in (0, n_views // 2, n_views - 1):
-        L.qr_sh_to_rgb(_t(mu), _t(sh), 3, cams[v], one)
+        L.qr_sh_to_rgb(_t(mu), _t(sh), degree, cams[v], one)
         torch.cuda.synchronize()
         np.testing.assert_allclose(out[v].cpu().numpy(), one.cpu().numpy(), rtol=0, atol=1e-6)
-        want = oracle.sh_to_rgb(mu.astype(np.float64), sh.astype(np.float64), cams[v], 3)
+        want = oracle.sh_to_rgb(mu.astype(np.float64), sh.astype(np.float64), cams[v], degree)
         np.testing.assert_allclose(out[v, :, :3].cpu().numpy(), want, atol=2e-6)
     assert torch.all(out[:, :, 3:] == 0)
