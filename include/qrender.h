@@ -436,7 +436,11 @@ int qr_render_quantile_batched_backward(void* stream, int32_t n_views, const qr_
  * device f32[n, coef_stride, 3], coef_stride >= (degree+1)^2; cam: host.
  * Writes out (device f32[n, out_dim], out_dim >= 3): the colour in columns
  * 0..2, zeros in the rest (a feature table for the renderers, whose dim must
- * be a multiple of 16). degree in [0, 3].
+ * be a multiple of 16). degree in [0, 3]. The caller owns every buffer; the
+ * call only enqueues work on `stream`. Errors: QR_ERR_INVALID_ARG for n < 0,
+ * coef_stride < (degree+1)^2, out_dim < 3, a null camera or (n > 0) a null
+ * array; QR_ERR_UNSUPPORTED for a degree outside [0, 3] or n >= 2^39;
+ * QR_ERR_HIP for a failed launch. n = 0 does nothing.
  */
 int qr_sh_to_rgb(void* stream, int64_t n, int32_t degree, const float* means3d, const float* sh,
                  int32_t coef_stride, const qr_camera* cam, float* out, int32_t out_dim);
@@ -448,8 +452,9 @@ int qr_sh_to_rgb(void* stream, int64_t n, int32_t degree, const float* means3d, 
  * array of n_views cameras (their centres are copied into the launch
  * arguments; the call keeps no pointer). out: device f32[n_views, n,
  * out_dim]; view v's table starts at out + v*n*out_dim, out_dim a positive
- * multiple of 4 (16-byte rows). Errors: as qr_sh_to_rgb, QR_ERR_INVALID_ARG
- * for n_views <= 0, QR_ERR_UNSUPPORTED for out_dim not a multiple of 4.
+ * multiple of 4 (16-byte rows; out 16-byte aligned). Errors: as
+ * qr_sh_to_rgb, QR_ERR_INVALID_ARG for n_views <= 0, QR_ERR_UNSUPPORTED for
+ * out_dim not a multiple of 4 or n*out_dim/4 >= 2^39.
  */
 int qr_sh_to_rgb_views(void* stream, int64_t n, int32_t degree, const float* means3d,
                        const float* sh, int32_t coef_stride, const qr_camera* cams,
