@@ -271,3 +271,17 @@ def test_product_path_does_not_touch_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"\boracle\b", src), f
+
+
+def test_binding_constants_match_the_header(L):
+    """Every enumerator and #define constant the binding mirrors has the
+    header's value (the selection rules, reductions, dtypes, error codes,
+    limits)."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    values = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(QR_[A-Z0-9_]+)\s*=\s*(-?\d+)", src)}
+    values.update({m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(QR_[A-Z0-9_]+)\s+(\d+)\b", src)})
+    mirrored = [n for n in dir(L) if n.startswith("QR_") and isinstance(getattr(L, n), int)]
+    assert {"QR_SELECT_TOPK", "QR_SELECT_STRATIFIED", "QR_REDUCE_MEAN", "QR_FP8_E4M3"} <= set(mirrored)
+    for n in mirrored:
+        assert n in values, n
+        assert getattr(L, n) == values[n], (n, getattr(L, n), values[n])
