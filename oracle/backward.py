@@ -26,6 +26,15 @@ c dy^2), dx = px + 0.5 - u, dy = py + 0.5 - v:
   dpower/da = -dx^2/2, dpower/db = -dx dy, dpower/dc = -dy^2/2,
   dpower/du = a dx + b dy, dpower/dv = b dx + c dy.
 The conic is parameterised by (a, b, c) with b the single off-diagonal entry.
+
+Magnitudes (``magnitude=True``, for tolerances only): alongside each gradient
+the oracle returns, per element, a bound on the sum of the absolute values
+of the terms that a finite-precision evaluation adds up to form it - every
+dot product <g, f> replaced by sum |g| |f|, every tail sum by the whole
+ray's sum of w_l sum |g| |f_l| (an evaluation may form tail sums as a total
+minus a prefix), and each chain-rule factor by its absolute value. A
+float32 evaluation of the same sums errs by at most a small multiple of its
+unit roundoff times this bound, element by element.
 """
 
 from __future__ import annotations
@@ -56,11 +65,20 @@ def _entries(proj, lst, px, py, params):
     return out
 
 
-def _chain(grads, proj, e, dL_dalpha):
+def _chain(grads, proj, e, dL_dalpha, mag=None, mag_dalpha=0.0):
     g, alpha, G, dx, dy, clamped = e
     if clamped:
         return
     a, b, c = proj["conic"][g]
+    if mag is not None:
+        m = abs(mag_dalpha)
+        mag["opacity"][g] += m * G
+        mp = m * alpha
+        mag["conic"][g, 0] += mp * 0.5 * dx * dx
+        mag["conic"][g, 1] += mp * abs(dx * dy)
+        mag["conic"][g, 2] += mp * 0.5 * dy * dy
+        mag["means2d"][g, 0] += mp * (abs(a * dx) + abs(b * dy))
+        mag["means2d"][g, 1] += mp * (abs(b * dx) + abs(c * dy))
     grads["opacity"][g] += dL_dalpha * G
     dpow = dL_dalpha * alpha
     grads["conic"][g, 0] += dpow * (-0.5 * dx * dx)
@@ -92,13 +110,15 @@ def _pixels_of_tiles(width, height, tile, tiles=None):
 
 
 def dense_backward(proj, sorted_gid, tile_offsets, features, width, height, grad_out,
-                   params: RenderParams = RenderParams(), tiles=None):
+                   params: RenderParams = RenderParams(), tiles=None, magnitude=False):
     """Gradients of the dense blend; with ``tiles`` only those tiles' pixels
-    contribute (as if grad_out were zero elsewhere)."""
+    contribute (as if grad_out were zero elsewhere). With ``magnitude`` the
+    result also holds "abs", the per-element term magnitudes (module doc)."""
     proj = _proj64(proj)
     F = np.asarray(features, np.float64)
     gout = np.asarray(grad_out, np.float64)
     grads = _new_grads(F.shape[0], F.shape[1])
+    mag = _new_grads(F.shape[0], F.shape[1]) if magnitude else None
     for t, px, py in _pixels_of_tiles(width, height, params.tile, tiles):
         lst = sorted_gid[int(tile_offsets[t]):int(tile_offsets[t + 1])]
         T = 1.0
@@ -111,24 +131,35 @@ def dense_backward(proj, sorted_gid, tile_offsets, features, width, height, grad
             T = T_test
         gp = gout[py, px]
         d = [float(F[e[0]] @ gp) for e, _ in blended]
+        if mag is not None:
+            dabs = [float(np.abs(F[e[0]]) @ np.abs(gp)) for e, _ in blended]
+            ray_abs = sum(Tj * e[1] * da for (e, Tj), da in zip(blended, dabs))
         suffix = 0.0
         for j in range(len(blended) - 1, -1, -1):
             e, Tj = blended[j]
             w = Tj * e[1]
             grads["features"][e[0]] += w * gp
             dL_da = Tj * d[j] - suffix / (1.0 - e[1])
-            _chain(grads, proj, e, dL_da)
+            m_da = 0.0
+            if mag is not None:
+                mag["features"][e[0]] += w * np.abs(gp)
+                m_da = Tj * dabs[j] + ray_abs / (1.0 - e[1])
+            _chain(grads, proj, e, dL_da, mag, m_da)
             suffix += w * d[j]
+    if mag is not None:
+        grads["abs"] = mag
     return grads
 
 
 def quantile_backward(proj, sorted_gid, tile_offsets, features, width, height, K, grad_out,
-                      params: RenderParams = RenderParams(), tiles=None):
-    """Gradients of Quantile Rendering; ``tiles`` as in dense_backward."""
+                      params: RenderParams = RenderParams(), tiles=None, magnitude=False):
+    """Gradients of Quantile Rendering; ``tiles`` and ``magnitude`` as in
+    dense_backward."""
     proj = _proj64(proj)
     F = np.asarray(features, np.float64)
     gout = np.asarray(grad_out, np.float64)
     grads = _new_grads(F.shape[0], F.shape[1])
+    mag = _new_grads(F.shape[0], F.shape[1]) if magnitude else None
     thr = np.append(quantile_thresholds(K), 0.0)
     for t, px, py in _pixels_of_tiles(width, height, params.tile, tiles):
         lst = sorted_gid[int(tile_offsets[t]):int(tile_offsets[t + 1])]
@@ -152,6 +183,9 @@ def quantile_backward(proj, sorted_gid, tile_offsets, features, width, height, K
         fsum = sum(TQj * e[1] * F[e[0]] for e, TQj in sel)
         gf = float(gp @ (fsum / Z))
         d = [float(F[e[0]] @ gp) for e, _ in sel]
+        if mag is not None:
+            dabs = [float(np.abs(F[e[0]]) @ np.abs(gp)) for e, _ in sel]
+            ray_abs = sum(TQj * e[1] * da for (e, TQj), da in zip(sel, dabs))
         suffix = 0.0
         for j in range(len(sel) - 1, -1, -1):
             e, TQj = sel[j]
@@ -159,6 +193,13 @@ def quantile_backward(proj, sorted_gid, tile_offsets, features, width, height, K
             grads["features"][e[0]] += (w / Z) * gp
             dL_da = (TQj * d[j] - suffix / (1.0 - e[1])) / Z \
                 - gf * TQ / ((1.0 - e[1]) * Z)
-            _chain(grads, proj, e, dL_da)
+            m_da = 0.0
+            if mag is not None:
+                mag["features"][e[0]] += (w / Z) * np.abs(gp)
+                m_da = (TQj * dabs[j] + ray_abs / (1.0 - e[1])) / Z \
+                    + (ray_abs / Z) * TQ / ((1.0 - e[1]) * Z)
+            _chain(grads, proj, e, dL_da, mag, m_da)
             suffix += w * d[j]
+    if mag is not None:
+        grads["abs"] = mag
     return grads

@@ -66,6 +66,13 @@ def _alpha(proj, g, xs, ys, params):
     return np.minimum(params.alpha_max, o * np.exp(power))
 
 
+def _dense_weight(alpha, T_before, T_after):
+    """Eq. 1's weight of an entry: its opacity times the transmittance in
+    front of it (T_after = T_before (1 - alpha) is the transmittance behind
+    it, which the weight must not use)."""
+    return alpha * T_before
+
+
 def _rel(x, bound):
     return np.abs(x - bound) / bound
 
@@ -125,7 +132,7 @@ def render_dense(proj, sorted_gid, tile_offsets, features, width, height,
                 marg[on_ray] = np.minimum(marg[on_ray], _rel(T_test[on_ray], params.T_eps))
             stop = on_ray & (T_test < t_eps)
             blend = on_ray & ~stop
-            w = np.where(blend, alpha * T, 0.0)
+            w = np.where(blend, _dense_weight(alpha, T, T_test), 0.0)
             C += w[:, None] * F[g][None, :]
             T = np.where(blend, T_test, T)
             ncon[blend] = pos - lo + 1
@@ -143,7 +150,9 @@ def render_quantile(proj, sorted_gid, tile_offsets, features, width, height, K,
     """Quantile Rendering (Algorithm 1) of every pixel's ray list.
 
     Returns dict: out [H,W,D] (normalised f~Q), T_q [H,W] (T^Q), n_sel [H,W]
-    (number of selected Gaussians), k [H,W] (thresholds consumed), n_steps
+    (number of selected Gaussians), k [H,W] (thresholds consumed), T_final
+    [H,W] (Algorithm 1's full transmittance T when the walk ends: the stop
+    test breaks before T takes the stopping entry's T_test), n_steps
     [H,W] (list position + 1 of the last on-ray entry examined, the stopping
     entry included), n_on [H,W] (on-ray entries examined),
     sel_gid [H,W,K] (-1 padded, in selection order), sel_w [H,W,K] (w^Q),
@@ -165,6 +174,7 @@ def render_quantile(proj, sorted_gid, tile_offsets, features, width, height, K,
     T_q = np.full((height, width), np.nan)
     n_sel = np.full((height, width), -1, dtype=np.int64)
     k_out = np.full((height, width), -1, dtype=np.int64)
+    T_fin = np.full((height, width), np.nan)
     n_steps = np.full((height, width), -1, dtype=np.int64)
     n_on = np.full((height, width), -1, dtype=np.int64)
     sel_gid = np.full((height, width, K), -1, dtype=np.int64)
@@ -226,11 +236,12 @@ def render_quantile(proj, sorted_gid, tile_offsets, features, width, height, K,
         T_q[ys, xs] = TQ
         n_sel[ys, xs] = ns
         k_out[ys, xs] = k
+        T_fin[ys, xs] = T
         n_steps[ys, xs] = steps
         n_on[ys, xs] = non
         sel_gid[ys, xs] = sg
         sel_w[ys, xs] = sw
         sel_pos[ys, xs] = sp
         margin[ys, xs] = marg
-    return dict(out=out, T_q=T_q, n_sel=n_sel, k=k_out, n_steps=n_steps, n_on=n_on,
+    return dict(out=out, T_q=T_q, n_sel=n_sel, k=k_out, T_final=T_fin, n_steps=n_steps, n_on=n_on,
                 sel_gid=sel_gid, sel_w=sel_w, sel_pos=sel_pos, margin=margin)

@@ -61,12 +61,15 @@ def stratified_thresholds(mu: float, sigma: float, K: int) -> np.ndarray:
 
 
 def render_stratified(proj, sorted_gid, tile_offsets, features, width, height, K,
-                      params: RenderParams = RenderParams(), tiles=None):
+                      params: RenderParams = RenderParams(), tiles=None, bias=0.0):
     """Stratified-K render of every pixel's ray list. Returns dict: out [H,W,D],
     T_q [H,W], n_sel [H,W], sel_gid [H,W,K] (-1 padded), sel_w [H,W,K],
     mu [H,W], sigma [H,W], margin [H,W] (smallest relative distance of a
     decision of the second pass - alpha' vs alpha_min, T_test vs a threshold
-    - to its boundary, and of the first pass's T_test vs T_eps)."""
+    - to its boundary, and of the first pass's T_test vs T_eps). ``bias``
+    moves every boundary (alpha_min, T_eps, each threshold) by the factor
+    (1 + bias), as in render.py, to produce the result a lower-precision
+    walk may legitimately give where a margin is tiny."""
     proj = _as_f64_proj(proj)
     F = np.asarray(features, dtype=np.float64)
     D = F.shape[1]
@@ -81,6 +84,8 @@ def render_stratified(proj, sorted_gid, tile_offsets, features, width, height, K
     mu_out = np.full((height, width), np.nan)
     sd_out = np.full((height, width), np.nan)
     margin = np.full((height, width), np.nan)
+    a_min = params.alpha_min * (1.0 + bias)
+    t_eps = params.T_eps * (1.0 + bias)
     if tiles is None:
         tiles = range(tiles_x * tiles_y)
     for t in tiles:
@@ -90,7 +95,7 @@ def render_stratified(proj, sorted_gid, tile_offsets, features, width, height, K
         A = np.array([_alpha(proj, g, xs, ys, params) for g in gids]).reshape(len(gids), xs.size)
         for j in range(xs.size):
             a_all = A[:, j]
-            on = a_all >= params.alpha_min
+            on = a_all >= a_min
             marg = np.min(_rel(a_all, params.alpha_min)) if a_all.size else np.inf
             # pass 1: transmittance statistics along the ray
             T = 1.0
@@ -98,24 +103,25 @@ def render_stratified(proj, sorted_gid, tile_offsets, features, width, height, K
             for a in a_all[on]:
                 T_test = T * (1.0 - a)
                 marg = min(marg, abs(T_test - params.T_eps) / params.T_eps)
-                if T_test < params.T_eps:
+                if T_test < t_eps:
                     break
                 T = T_test
                 vals.append(T)
             mu, sd = float(np.mean(vals)), float(np.std(vals))
             thr = np.append(stratified_thresholds(mu, sd, K), -1.0)  # t_{K+1}: never crossed
+            thr_b = thr * (1.0 + bias)
             # pass 2: Algorithm 1 with the ray's thresholds
             T, TQ, k, ns = 1.0, 1.0, 0, 0
             fQ = np.zeros(D)
             for i in np.nonzero(on)[0]:
                 a = a_all[i]
                 T_test = T * (1.0 - a)
-                if T_test < params.T_eps:  # the dense stop ends the sampled ray
+                if T_test < t_eps:  # the dense stop ends the sampled ray
                     break
                 live = thr[:K][thr[:K] > 0.0]
                 if live.size:
                     marg = min(marg, float(np.min(np.abs(T_test - live) / live)))
-                if T_test < thr[k]:
+                if T_test < thr_b[k]:
                     k += 1
                     w = TQ * a
                     fQ += w * F[gids[i]]
@@ -123,7 +129,7 @@ def render_stratified(proj, sorted_gid, tile_offsets, features, width, height, K
                     sel_gid[ys[j], xs[j], ns] = gids[i]
                     sel_w[ys[j], xs[j], ns] = w
                     ns += 1
-                    while T_test < thr[k]:
+                    while T_test < thr_b[k]:
                         k += 1
                 T = T_test
                 if k == K:

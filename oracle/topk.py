@@ -18,7 +18,9 @@ Readings (the paper names the strategy but not its details):
 Margins: as the dense oracle's (alpha' vs alpha_min, T_test vs T_eps), plus
 the relative gap between the K-th and (K+1)-th largest weights, where a float32
 ranking may legitimately differ. ``bias`` moves alpha_min and T_eps as in the
-dense oracle.
+dense oracle; ``swap_kth`` keeps the (K+1)-th largest weight instead of the
+K-th on every ray with more than K candidates (the other ranking a float32
+comparison may take where the two are nearly equal).
 """
 
 from __future__ import annotations
@@ -30,7 +32,7 @@ from .render import _alpha, _as_f64_proj, _rel, _tile_pixels
 
 
 def render_topk(proj, sorted_gid, tile_offsets, features, width, height, K,
-                params: RenderParams = RenderParams(), tiles=None, bias=0.0):
+                params: RenderParams = RenderParams(), tiles=None, bias=0.0, swap_kth=False):
     """Top-K rendering of every pixel's ray.
 
     Returns dict: out [H,W,D], T_q [H,W] (1 - sum of the selected weights),
@@ -100,6 +102,8 @@ def render_topk(proj, sorted_gid, tile_offsets, features, width, height, K,
             if len(c) > K:
                 wk, wk1 = wv[rank[K - 1]], wv[rank[K]]
                 marg[p] = min(marg[p], (wk - wk1) / wk)
+                if swap_kth:
+                    rank[[K - 1, K]] = rank[[K, K - 1]]
             keep = np.sort(rank[:K])  # back to list order
             s = wv[keep].sum()
             out[y, x] = (wv[keep][:, None] * F[gv[keep]]).sum(axis=0) / s

@@ -123,3 +123,28 @@ def test_dense_single_gaussian_closed_form():
     np.testing.assert_allclose(gr["features"][0], 0.4 * g[0, 0])
     # zero conic: G = 1, so dL/do = dL/dalpha'
     assert gr["opacity"][0] == pytest.approx(float(g[0, 0] @ f[0]))
+
+
+@pytest.mark.parametrize("quantile", [False, True])
+def test_term_magnitudes_bound_the_gradients(fd_case, quantile):
+    """The magnitudes (a tolerance scale) bound every gradient entry from
+    above, leave the gradients themselves unchanged, and equal the feature
+    gradient exactly when every term is non-negative (g >= 0: the feature
+    terms are w g / Z >= 0)."""
+    c = fd_case
+    feats = c["sc"].features.astype(np.float64)
+    tiles = [0, 3]
+    call = ((lambda g, **kw: oracle.quantile_backward(c["proj"], c["gids"], c["offs"], feats, 32, 32, K, g,
+                                                     tiles=tiles, **kw))
+            if quantile else
+            (lambda g, **kw: oracle.dense_backward(c["proj"], c["gids"], c["offs"], feats, 32, 32, g,
+                                                   tiles=tiles, **kw)))
+    plain = call(c["gout"])
+    r = call(c["gout"], magnitude=True)
+    for k in ("features", "opacity", "conic", "means2d"):
+        np.testing.assert_array_equal(r[k], plain[k])
+        assert np.all(r["abs"][k] >= np.abs(r[k]) * (1 - 1e-12)), k
+        assert np.all(r["abs"][k] >= 0)
+    assert np.count_nonzero(r["abs"]["means2d"]) > 0
+    pos = call(np.abs(c["gout"]), magnitude=True)
+    np.testing.assert_allclose(pos["abs"]["features"], pos["features"], rtol=1e-12, atol=0)

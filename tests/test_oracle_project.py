@@ -67,6 +67,35 @@ def test_on_axis_isotropic_closed_form():
     assert pr["depth"][0] == pytest.approx(3.0)
 
 
+@pytest.mark.parametrize("xz,yz", [(2.0, 0.5), (-0.4, -1.5), (1.2, 1.0), (0.3, -0.2)])
+def test_guard_band_clamps_the_jacobian(xz, yz):
+    """Isotropic Gaussian (s = 0.4) at camera-space x/z, y/z with R_cw = I and
+    z = 3: Sigma2D = s^2 J J^T + dilation I, where J is formed with x/z and
+    y/z clamped to guard x the half field of view of their own axis
+    (1.3 x 100 / 100 = 1.3 horizontally, 1.3 x 80 / 110 = 0.945 vertically
+    for this 200 x 160 camera with fx = 100, fy = 110). The cases clamp x
+    only, y only (at the negative limit), y only where swapping the image
+    sides (H for W) or the focal lengths would change which axis clamps, and
+    neither."""
+    cam = _cam(f=100.0)
+    prm = oracle.RenderParams()
+    z, s = 3.0, 0.4
+    pr = oracle.project(np.array([[xz * z, yz * z, 0.0]]), np.full((1, 3), s), np.array([[1.0, 0.0, 0.0, 0.0]]),
+                        np.array([0.9]), cam, prm)
+    lim_x = 1.3 * (cam.width / 2) / cam.fx
+    lim_y = 1.3 * (cam.height / 2) / cam.fy
+    xh, yh = min(max(xz, -lim_x), lim_x), min(max(yz, -lim_y), lim_y)
+    fx, fy = cam.fx, cam.fy
+    sxx = s * s * (fx / z) ** 2 * (1.0 + xh * xh) + prm.dilation
+    sxy = s * s * (fx * fy / (z * z)) * xh * yh
+    syy = s * s * (fy / z) ** 2 * (1.0 + yh * yh) + prm.dilation
+    np.testing.assert_allclose(pr["cov2d"][0], [sxx, sxy, syy], rtol=1e-10)
+    det = sxx * syy - sxy * sxy
+    np.testing.assert_allclose(pr["conic"][0], [syy / det, -sxy / det, sxx / det], rtol=1e-10)
+    # the mean itself is projected without the clamp
+    np.testing.assert_allclose(pr["means2d"][0], [fx * xz + cam.cx, fy * yz + cam.cy], rtol=1e-12)
+
+
 def _pinhole(p, cam):
     return np.array([cam.fx * p[0] / p[2] + cam.cx, cam.fy * p[1] / p[2] + cam.cy])
 

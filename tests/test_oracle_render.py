@@ -93,6 +93,48 @@ def test_tiled_equals_brute_force_ragged_image():
     _check_tiled_equals_brute(sc, cam, 4)
 
 
+# Algorithm 1's full transmittance T when the walk ends and the position of
+# the last entry it examined, walked by hand on the golden rays (the stop test
+# breaks before T takes the stopping entry's T_test):
+#   A (K=3, 0.5 x4): T 1 -> 1/2 -> 1/4; entry 2 crosses t_3 = 1/4 and stops -> T = 1/4, 3 entries
+#   B (K=3, 0.2 x8): entry 6 (T_test = 0.2097152) stops; T = 0.8^6 = 0.262144, 7 entries
+#   C (K=3, 0.9, ...): entry 0 crosses all three thresholds and stops -> T = 1, 1 entry
+#   D (K=1, 0.3 x4): entry 1 (T_test = 0.49 < 1/2) stops -> T = 0.7, 2 entries
+#   F (K=3, 0.1): no stop, the list ends -> T = 0.9, 1 entry
+HAND_T_FINAL = {"A_strict_threshold": ("1/4", 3), "B_residual_transmittance": ("4096/15625", 7),
+                "C_one_step_crosses_all": ("1", 1), "D_median_K1": ("7/10", 2),
+                "F_nothing_selected": ("9/10", 1)}
+
+
+@pytest.mark.parametrize("ex", _golden(), ids=lambda e: e["name"])
+def test_hand_worked_final_transmittance(ex):
+    if ex["name"] not in HAND_T_FINAL:
+        pytest.skip("no hand value")
+    T_fin, last = HAND_T_FINAL[ex["name"]]
+    proj, gids, offs, feats = ray_case(ex["alphas"])
+    q = oracle.render_quantile(proj, gids, offs, feats, 1, 1, ex["K"])
+    assert q["T_final"][0, 0] == pytest.approx(_frac(T_fin), rel=1e-14)
+    assert q["n_steps"][0, 0] == last
+
+
+def test_final_transmittance_of_unstopped_rays_is_the_full_product(tiny_case):
+    """A ray that never takes the stop test (k < K at the end of its list)
+    has T = the product of (1 - alpha') over its whole list: the dense blend
+    with T_eps = 0 (no stop) gives the same value; a stopped ray ends with
+    T >= 1/(K+1) (T before the stopping entry passed the stop test)."""
+    tc = tiny_case
+    K = 8
+    feats = tc["scene"].features
+    q = oracle.render_quantile(tc["proj"], tc["gids"], tc["offs"], feats, 64, 64, K, tc["params"])
+    prm0 = oracle.RenderParams(T_eps=0.0)
+    d = oracle.render_dense(tc["proj"], tc["gids"], tc["offs"], feats, 64, 64, prm0)
+    unstopped = q["k"] < K
+    assert unstopped.mean() > 0.2 and (~unstopped).mean() > 0.1
+    np.testing.assert_allclose(q["T_final"][unstopped], d["T_final"][unstopped], rtol=1e-12)
+    assert np.all(q["T_final"][~unstopped] >= 1.0 / (K + 1) * (1 - 1e-12))
+    assert np.all(q["T_final"][unstopped] <= 1.0)
+
+
 def test_partition_of_unity_and_constant_features(tiny_case):
     """Sum_i w_i + T_final = 1, hence a constant feature c renders (1-T_final) c
     densely; quantile weights satisfy sum w^Q + T^Q = 1, so Q renders c."""
@@ -206,12 +248,8 @@ def test_planted_mistakes_are_caught(monkeypatch, tiny_case):
     monkeypatch.setattr(R, "_alpha", bad_alpha)
     _expect_failure(lambda: test_tiled_equals_brute_force_tiny(tiny_case))
     monkeypatch.setattr(R, "_alpha", orig_alpha)
-    # (3) transmittance updated before the weight is taken
-    orig_rd = R.render_dense
-
-    def bad_dense(proj, sorted_gid, tile_offsets, features, width, height, params=oracle.RenderParams(), tiles=None, bias=0.0):
-        r = orig_rd(proj, sorted_gid, tile_offsets, features, width, height, params, tiles, bias)
-        r["out"] = r["out"] * 0.999
-        return r
-    monkeypatch.setattr(oracle, "render_dense", bad_dense)
+    # (3) transmittance updated before the weight is taken: w = alpha T_{i+1}
+    orig_w = R._dense_weight
+    monkeypatch.setattr(R, "_dense_weight", lambda alpha, T_before, T_after: alpha * T_after)
     _expect_failure(lambda: test_partition_of_unity_and_constant_features(tiny_case))
+    monkeypatch.setattr(R, "_dense_weight", orig_w)
