@@ -44,14 +44,21 @@ extern "C" {
 #endif
 
 #define QR_TILE 16
-#define QR_MAX_K 32        /* largest number of quantile Gaussians per ray */
-#define QR_MAX_DIM 4096    /* largest feature width D */
+/* K (quantile Gaussians per ray) ranges over [1, QR_MAX_K] in every entry
+ * point, backward passes included: the paper trains at K = 40 and sweeps K up
+ * to 50. A workgroup keeps each pixel's <= K selections in LDS (8 bytes
+ * each), so K above about 40 leaves room for one workgroup per CU. */
+#define QR_MAX_K 64
+/* Feature width D: a positive multiple of 16 (the column block of the matrix
+ * core contractions of the dense blend and the backward passes) up to
+ * QR_MAX_DIM. */
+#define QR_MAX_DIM 4096
 #define QR_BATCH_TILE_BITS 20  /* batched schedule item = (view << 20) | tile */
 
 typedef enum qr_status {
   QR_OK = 0,
   QR_ERR_INVALID_ARG = -1, /* null pointer, non-positive size, bad range */
-  QR_ERR_UNSUPPORTED = -2, /* dtype, D not a multiple of 16, K out of range */
+  QR_ERR_UNSUPPORTED = -2, /* dtype, D not a multiple of 16, K outside [1, QR_MAX_K] */
   QR_ERR_CAPACITY = -3,    /* workspace or pair capacity too small */
   QR_ERR_HIP = -4          /* a HIP runtime call or launch failed */
 } qr_status;
@@ -223,8 +230,12 @@ int qr_bin_sort_workspace_size(int64_t n, int32_t tiles_x, int32_t tiles_y,
  * sequence S_r of Eq. 1, built per tile as in 3D-GS).
  *
  * Emits one pair per tile in each tile_rect, keyed (tile id << 32) | bits of
- * the float32 depth, and sorts the keys with a stable LSD radix sort in
- * Gaussian-index order, so each tile's list is ordered by (depth, index).
+ * the float32 depth: a bucket sort by tile (count, exclusive scan, scatter
+ * into each tile's range) followed by an independent sort of each tile's
+ * bucket by (depth bits << 32 | Gaussian index) - a bitonic sort in LDS for
+ * buckets of up to 2,048 keys, a single-workgroup LSD radix sort through the
+ * workspace for longer ones. The keys are unique, so each tile's list is
+ * ordered by (depth, index) whatever order the scatter produced.
  * Inputs: tile_rect, tiles_touched, depth as written by qr_project.
  * Outputs: sorted_gid u32[capacity] (Gaussian index of each sorted pair);
  * sorted_keys u64[capacity] (nullable; the sorted keys); tile_offsets
@@ -292,10 +303,16 @@ int qr_render_dense(void* stream, int32_t width, int32_t height,
  *   was selected. Thresholds t_m = 1 - m/(K+1) are rounded once to float32;
  *   the comparison is strict.
  * Inputs as qr_render_dense; 1 <= K <= QR_MAX_K.
- * Outputs: out f32[H,W,dim]; T_q f32[H,W] (nullable); n_sel i32[H,W]
- * (nullable; number of selected Gaussians); sel_gid i32[H,W,K] and sel_w
- * f32[H,W,K] (nullable; selected Gaussian indices in ray order and their
- * weights w^Q, padded with -1 / 0).
+ * Outputs: out f32[H,W,dim]; T_q f32[H,W] (nullable; T^Q); n_sel i32[H,W]
+ * (nullable; number of selected Gaussians); T_final f32[H,W] (nullable;
+ * Algorithm 1's full transmittance T when the walk ends: the stop test
+ * breaks before T takes the stopping entry's T_test, so a stopped ray
+ * reports T >= 1/(K+1)); last_pos i32[H,W] (nullable; tile-list position + 1
+ * of the last entry on the ray that the walk examined, the stopping entry
+ * included; 0 if none); sel_gid i32[H,W,K] and sel_w f32[H,W,K] (nullable;
+ * selected Gaussian indices in ray order and their weights w^Q, padded with
+ * -1 / 0). T_final and last_pos are defined for QR_SELECT_QUANTILE only
+ * (QR_ERR_UNSUPPORTED if requested with another rule).
  */
 int qr_render_quantile(void* stream, int32_t width, int32_t height,
                        const qr_params* prm, int32_t K,
@@ -304,6 +321,7 @@ int qr_render_quantile(void* stream, int32_t width, int32_t height,
                        const void* features, int32_t dtype,
                        const float* feature_scale, int32_t dim,
                        float* out, float* T_q, int32_t* n_sel,
+                       float* T_final, int32_t* last_pos,
                        int32_t* sel_gid, float* sel_w);
 
 /*
@@ -350,7 +368,13 @@ int qr_batch_schedule(void* stream, int32_t n_views, const qr_view* views,
 
 /*
  * qr_render_dense_backward / qr_render_quantile_backward - gradients of the
- * two renderers given dL/d(out) = grad_out f32[H,W,dim]. The forward walk is
+ * two renderers given dL/d(out) = grad_out f32[H,W,dim]: the paper trains
+ * its feature network through the renderer (Sec. 4.2 and Sec. 4.3: the
+ * image-space contrastive loss of Eq. 2 is back-propagated through the
+ * rendered feature map to the per-Gaussian features), and the same chain
+ * gives the gradients of the 2D means, conics and opacities. The
+ * derivatives are those of Eq. 1 (dense) and of Algorithm 1 (quantile) with
+ * the discrete decisions held fixed. The forward walk is
  * recomputed (same float32 arithmetic, so the same entries are blended or
  * selected) and transmittance is recovered in a reverse sweep. Discrete
  * decisions pass no gradient; a clamped alpha' passes none to o or geometry.
@@ -405,8 +429,10 @@ int qr_autotune_batched(void* stream, int32_t n_views, const qr_view* views,
                         int32_t* best_wg_per_cu);
 
 /*
- * qr_render_quantile_batched_backward - qr_render_quantile_backward for many
- * views in one launch over the (view, tile) items of `schedule`, the same
+ * qr_render_quantile_batched_backward - qr_render_quantile_backward (the
+ * gradients of Algorithm 1 that training through the renderer needs,
+ * Sec. 4.2) for many views in one launch over the (view, tile) items of
+ * `schedule`, the same
  * schedule format and launch modes as qr_render_quantile_batched (n_workgroups
  * = 0: one workgroup per item; > 0: persistent workgroups on per-XCD work
  * queues held in `workspace`, device, >= 32 bytes). `views` (device

@@ -24,7 +24,7 @@ QR_F32, QR_BF16, QR_FP8_E4M3 = 0, 1, 2
 QR_SELECT_QUANTILE, QR_SELECT_STRATIFIED, QR_SELECT_TOPK = 0, 1, 2
 QR_REDUCE_MAX, QR_REDUCE_MEAN = 0, 1
 QR_TILE = 16
-QR_MAX_K = 32
+QR_MAX_K = 64
 
 EXPORTED = [
     "qr_version", "qr_last_error", "qr_project", "qr_count_pairs",
@@ -88,7 +88,7 @@ def _load():
         "qr_project_views": ([P, i64, P, P, P, P, i32, cam_p, prm_p, P, P, P, P, P], i32),
         "qr_bin_sort_views": ([P, i32, i64, i32, i32, P, P, P, i64, P, sz, P, P, P, P], i32),
         "qr_render_dense": ([P, i32, i32, prm_p, P, P, P, P, P, i32, P, i32, P, P, P], i32),
-        "qr_render_quantile": ([P, i32, i32, prm_p, i32, P, P, P, P, P, i32, P, i32, P, P, P, P, P], i32),
+        "qr_render_quantile": ([P, i32, i32, prm_p, i32, P, P, P, P, P, i32, P, i32, P, P, P, P, P, P, P], i32),
         "qr_render_dense_backward": ([P, i32, i32, prm_p, P, P, P, P, P, i32, P, i32, P, P, P, P, P], i32),
         "qr_render_quantile_backward": ([P, i32, i32, prm_p, i32, P, P, P, P, P, i32, P, i32, P, P, P, P], i32),
         "qr_quantize_features": ([P, i64, i32, P, i32, P, P], i32),
@@ -329,18 +329,21 @@ def qr_render_dense(width, height, params, tile_offsets, sorted_gid, means2d, co
 
 def qr_render_quantile(width, height, params, K, tile_offsets, sorted_gid, means2d, conic_opacity,
                        features, feature_scale, out, T_q=None, n_sel=None, sel_gid=None,
-                       sel_w=None, stream=None):
+                       sel_w=None, stream=None, T_final=None, last_pos=None):
     fp, code, sp, dim = _feat_args(features, feature_scale)
     npx = _check_render(width, height, tile_offsets, sorted_gid, means2d, conic_opacity, features)
     _need(out, npx * dim, (torch.bfloat16,) if params.out_dtype == QR_BF16 else F32, "out")
     _need(T_q, npx, F32, "T_q")
     _need(n_sel, npx, I32, "n_sel")
+    _need(T_final, npx, F32, "T_final")
+    _need(last_pos, npx, I32, "last_pos")
     _need(sel_gid, npx * K, I32, "sel_gid")
     _need(sel_w, npx * K, F32, "sel_w")
     _check(_LIB.qr_render_quantile(_stream(stream), width, height, ctypes.byref(params), K,
                                    _ptr(tile_offsets), _ptr(sorted_gid), _ptr(means2d),
                                    _ptr(conic_opacity), fp, code, sp, dim, _ptr(out), _ptr(T_q),
-                                   _ptr(n_sel), _ptr(sel_gid), _ptr(sel_w)))
+                                   _ptr(n_sel), _ptr(T_final), _ptr(last_pos), _ptr(sel_gid),
+                                   _ptr(sel_w)))
 
 
 def qr_render_dense_backward(width, height, params, tile_offsets, sorted_gid, means2d,

@@ -27,11 +27,65 @@ from .render import tiles_of
 SCHEDULES = ("natural", "heavy")
 
 
+def _check_tensor(t, numel, dtypes, name, device):
+    """Shape, dtype, layout and device of one view array (dtype and size
+    first, so that the message names the mismatch that matters)."""
+    if t is None:
+        raise ValueError("%s is required" % name)
+    if t.dtype not in dtypes:
+        raise TypeError("%s: dtype %s, expected one of %s" % (name, t.dtype, dtypes))
+    if t.numel() < numel:
+        raise ValueError("%s has %d elements, needs %d" % (name, t.numel(), numel))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.device != device:
+        raise ValueError("%s is on %s, the batch on %s" % (name, t.device, device))
+
+
+def validate_views(views, K: int, dim: int, dtype_code: int, params):
+    """Host-side checks of every view record before its pointers are packed
+    into the device table: the batched kernels read sizes from the records
+    and cannot check the buffers behind them, so a mismatch here would be an
+    out-of-bounds access there. Raises TypeError / ValueError naming the view
+    and field."""
+    if not views:
+        raise ValueError("a batch needs at least one view")
+    if not 1 <= K <= L.QR_MAX_K:
+        raise ValueError("K = %d outside [1, %d]" % (K, L.QR_MAX_K))
+    out_dt = (torch.bfloat16,) if params.out_dtype == L.QR_BF16 else L.F32
+    feat_dt = tuple(t for t, c in L.DTYPE_CODE.items() if c == dtype_code)
+    dev = views[0]["out"].device
+    for i, v in enumerate(views):
+        W, H = int(v["width"]), int(v["height"])
+        if W <= 0 or H <= 0:
+            raise ValueError("view %d: image size %dx%d" % (i, W, H))
+        tx, ty = tiles_of(W, H)
+        f = v["features"]
+        name = lambda k: "view %d: %s" % (i, k)
+        if f.dim() != 2 or f.shape[1] != dim:
+            raise ValueError("%s must be [N, %d], got %s" % (name("features"), dim, tuple(f.shape)))
+        n = f.shape[0]
+        _check_tensor(f, n * dim, feat_dt, name("features"), dev)
+        if dtype_code == L.QR_FP8_E4M3:
+            _check_tensor(v.get("feature_scale"), n, L.F32, name("feature_scale"), dev)
+        _check_tensor(v["tile_offsets"], tx * ty + 1, L.I32, name("tile_offsets"), dev)
+        _check_tensor(v["sorted_gid"], 1, L.I32, name("sorted_gid"), dev)
+        _check_tensor(v["means2d"], 2 * n, L.F32, name("means2d"), dev)
+        _check_tensor(v["conic_opacity"], 4 * n, L.F32, name("conic_opacity"), dev)
+        _check_tensor(v["out"], W * H * dim, out_dt, name("out"), dev)
+        if v.get("T_q") is not None:
+            _check_tensor(v["T_q"], W * H, L.F32, name("T_q"), dev)
+        if v.get("n_sel") is not None:
+            _check_tensor(v["n_sel"], W * H, L.I32, name("n_sel"), dev)
+
+
 class BatchedQuantile:
     def __init__(self, views, K: int, dim: int, dtype_code: int, params):
         """views: list of dicts with tile_offsets, sorted_gid, means2d,
         conic_opacity, features, feature_scale (or None), out, T_q, n_sel (or
-        None), width, height (all tensors on one device)."""
+        None), width, height (all tensors on one device); checked by
+        validate_views before anything is packed."""
+        validate_views(views, K, dim, dtype_code, params)
         self.n_views = len(views)
         self.K, self.dim, self.dtype_code, self.params = K, dim, dtype_code, params
         dev = views[0]["out"].device

@@ -102,6 +102,9 @@ __device__ __forceinline__ ViewArgs view_args(const qr_view& qv) {
 struct PixelSel {
   int ns;    // selections (0 outside the image)
   float TQ;  // T^Q after the last selection
+  float T;   // Algorithm 1: full transmittance when the walk ends (the stop
+             // test breaks before T takes the stopping entry's T_test)
+  int last;  // Algorithm 1: list position + 1 of the last on-ray entry examined
 };
 
 // The walk for one tile (all 256 threads of the workgroup). Selections go to
@@ -190,7 +193,7 @@ __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi
   };
 
   float T = 1.f, TQ = 1.f;
-  int k = 0, ns = 0;
+  int k = 0, ns = 0, last = 0;
   bool done = !inside;
   // t_{k+1}: changes only at a crossing
   float thr_k = MODE == QR_SELECT_STRATIFIED ? stratified_threshold(1, K, mu, sigma)
@@ -271,6 +274,7 @@ __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi
           done = true;
           continue;
         }
+        if constexpr (MODE == QR_SELECT_QUANTILE) last = batch + j + u - lo + 1;
         if (T_test < thr_k) {  // crossing: a quantile Gaussian
           my_pos[ns] = batch + j + u;
           my_w[ns] = TQ * alpha;
@@ -281,7 +285,8 @@ __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi
           thr_k = threshold(k);
           if (k == K) done = true;
         }
-        T = T_test;
+        // Algorithm 1 leaves T at the stopping entry (the stop test comes first)
+        if (MODE != QR_SELECT_QUANTILE || !done) T = T_test;
       }
     }
   }
@@ -305,13 +310,13 @@ __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi
     L.ns[tid] = inside ? ns : -1;
     L.inv[tid] = ns > 0 ? 1.f / sum : 0.f;
     wave_lds_sync();
-    return PixelSel{ns, TQ};
+    return PixelSel{ns, TQ, T, last};
   }
   L.ns[tid] = inside ? ns : -1;
   L.inv[tid] = ns > 0 ? 1.f / (1.f - TQ) : 0.f;
   wave_lds_sync();
 
-  return PixelSel{ns, TQ};
+  return PixelSel{ns, TQ, T, last};
 }
 
 // The merge for one tile (all 256 threads; wave-local), after the walk.

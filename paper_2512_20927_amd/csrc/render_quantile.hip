@@ -298,7 +298,9 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
                                               int* __restrict__ s_sel_gid,
                                               float* __restrict__ s_sel_w,
                                               int32_t* __restrict__ sel_gid_out,
-                                              float* __restrict__ sel_w_out) {
+                                              float* __restrict__ sel_w_out,
+                                              float* __restrict__ T_final_out,
+                                              int32_t* __restrict__ last_pos_out) {
   const int W = v.W, H = v.H;
   const int tiles_x = (W + kTile - 1) / kTile;
   const int tid = threadIdx.x;
@@ -339,6 +341,8 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
     const int pix = py * W + px;
     if (v.T_q) v.T_q[pix] = TQ;
     if (v.n_sel) v.n_sel[pix] = ns;
+    if (T_final_out) T_final_out[pix] = sel.T;
+    if (last_pos_out) last_pos_out[pix] = sel.last;
     if (sel_gid_out) {
       for (int j = 0; j < K; ++j) {
         sel_gid_out[static_cast<int64_t>(pix) * K + j] =
@@ -352,13 +356,14 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
 template <int DT, int OT, int MODE>
 __global__ void __launch_bounds__(kTilePix, kWavesPerSimd)
 render_quantile_kernel(ViewArgs v, int n_tiles, qr_params prm, int K, int dim,
-                       int32_t* __restrict__ sel_gid_out, float* __restrict__ sel_w_out) {
+                       int32_t* __restrict__ sel_gid_out, float* __restrict__ sel_w_out,
+                       float* __restrict__ T_final_out, int32_t* __restrict__ last_pos_out) {
   extern __shared__ unsigned char dyn_lds[];
   __shared__ QuantileLds L;
   int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);                            // [256][KP]
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);  // [256][KP]
   quantile_tile<DT, OT, MODE>(to_global(v), xcd_remap(blockIdx.x, n_tiles), K, dim, prm, L, s_sel_gid,
-                    s_sel_w, sel_gid_out, sel_w_out);
+                    s_sel_w, sel_gid_out, sel_w_out, T_final_out, last_pos_out);
 }
 
 // Many views in one persistent launch. The schedule is cut into one
@@ -409,7 +414,7 @@ render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t
     const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[item]);
     const GView v = to_global(view_args(views[packed >> kViewShift]));
     quantile_tile<DT, OT, MODE>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
-                      nullptr, nullptr);
+                      nullptr, nullptr, nullptr, nullptr);
   }
 }
 
@@ -429,7 +434,7 @@ render_quantile_batched_grid_kernel(const qr_view* __restrict__ views,
   const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[xcd_remap(blockIdx.x, n_items)]);
   const GView v = to_global(view_args(views[packed >> kViewShift]));
   quantile_tile<DT, OT, MODE>(v, static_cast<int>(packed & kTileMask), K, dim, prm, L, s_sel_gid, s_sel_w,
-                    nullptr, nullptr);
+                    nullptr, nullptr, nullptr, nullptr);
 }
 
 __global__ void reset_counter_kernel(uint32_t* __restrict__ c) {
@@ -467,7 +472,8 @@ extern "C" int qr_render_quantile(void* stream, int32_t width, int32_t height,
                                   const uint32_t* sorted_gid, const float* means2d,
                                   const float* conic_opacity, const void* features, int32_t dtype,
                                   const float* feature_scale, int32_t dim, float* out, float* T_q,
-                                  int32_t* n_sel, int32_t* sel_gid, float* sel_w) {
+                                  int32_t* n_sel, float* T_final, int32_t* last_pos,
+                                  int32_t* sel_gid, float* sel_w) {
   int rc = validate_render("qr_render_quantile", width, height, prm, tile_offsets, sorted_gid,
                            means2d, conic_opacity, features, dtype, feature_scale, dim, out);
   if (rc != QR_OK) return rc;
@@ -475,6 +481,9 @@ extern "C" int qr_render_quantile(void* stream, int32_t width, int32_t height,
     return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile: K = %d outside [1, %d]", K, QR_MAX_K);
   if ((sel_gid == nullptr) != (sel_w == nullptr))
     return fail(QR_ERR_INVALID_ARG, "qr_render_quantile: sel_gid and sel_w must both be given or both NULL");
+  if ((T_final || last_pos) && prm->selection != QR_SELECT_QUANTILE)
+    return fail(QR_ERR_UNSUPPORTED, "qr_render_quantile: T_final and last_pos are Algorithm 1's; "
+                "pass NULL with another selection rule");
   const int tiles_x = static_cast<int>(ceil_div(width, kTile));
   const int tiles_y = static_cast<int>(ceil_div(height, kTile));
   const int n_tiles = tiles_x * tiles_y;
@@ -486,7 +495,7 @@ extern "C" int qr_render_quantile(void* stream, int32_t width, int32_t height,
                    n_sel};
 #define QR_LAUNCH(DT, OT, SM)                                                                         \
   hipLaunchKernelGGL((render_quantile_kernel<DT, OT, SM>), dim3(n_tiles), dim3(kTilePix), lds, s, v,    \
-                     n_tiles, *prm, K, dim, sel_gid, sel_w)
+                     n_tiles, *prm, K, dim, sel_gid, sel_w, T_final, last_pos)
   QR_DISPATCH(dtype, prm->out_dtype, prm->selection);
 #undef QR_LAUNCH
   return check_launch("qr_render_quantile");

@@ -16,25 +16,28 @@
 // One workgroup per tile:
 //  1. the selection walk (quantile_select.h, the very code of the forward,
 //     so the same Gaussians are selected; nothing per pixel is stored by the
-//     forward). A tile selects a few dozen distinct Gaussians (about 20 on
-//     the room scenes, against about 1,200 pixel selections): they get slots
-//     0 .. 31 in list order, and each pixel a 32-bit mask of the slots it
-//     selected;
-//  2. dots D = G F^T: [256 px x dim] . [dim x slots] on
-//     v_mfma_f32_16x16x32_bf16 (each wave its 64 pixels), with d_pj read out
-//     at the selected (pixel, slot) pairs;
-//  3. a reverse sweep over each pixel's selections (thread per pixel) turns
-//     the dots into dL/dalpha' and the chain rule above, summed per slot in
-//     LDS and added to global memory once per (slot, value);
-//  4. feature gradients dF = W^T G: [slots x 256 px] . [256 px x dim] on the
-//     same MFMA (each wave a quarter of the columns), W[p][s] = w_ps / Z_p,
-//     one atomic per (slot, column).
+//     forward): each pixel's selected list positions and weights w^Q in LDS.
+//     A tile selects a few dozen distinct Gaussians (about 20 on the room
+//     scenes, against about 1,200 pixel selections): they get slots 0 .. 31
+//     in list order, and each pixel a 32-bit mask of the slots it selected;
+//  2. feature gradients dF = W^T G: [slots x 256 px] . [256 px x dim] on
+//     v_mfma_f32_16x16x32_bf16 (each wave a quarter of the columns),
+//     W[p][s] = w_ps / Z_p, one atomic per (slot, column);
+//  3. dots D = G F^T: [256 px x dim] . [dim x slots] on the same MFMA (each
+//     wave its 64 pixels), with d_pj read out at the selected (pixel, slot)
+//     pairs and written over the weights, which step 2 no longer needs (so
+//     a selection costs 8 bytes of LDS and K up to 64 fits);
+//  4. a sweep over each pixel's selections (thread per pixel) recomputes
+//     alpha'_j, w_j and T^Q_j from the records with the walk's own float
+//     operations and turns the dots into dL/dalpha' and the chain rule
+//     above, summed per slot in LDS and added to global memory once per
+//     (slot, value). The tail sums S_j are the total minus the running
+//     prefix, both kept in double.
 // Both products take float32 operands split into bfloat16 pairs
 // x = x_hi + x_lo and form hi.hi + hi.lo + lo.hi with float32 accumulation
 // (relative error below 2^-16 per product). Selections without a slot (a
 // tile with more than 32 distinct selections, or a position past kPosCap)
-// are handled by a plain wave-wide path. T^Q_j is recovered as
-// w_j / alpha'_j (alpha' >= alpha_min > 0 for every selection).
+// are handled by a plain wave-wide path.
 #include "quantile_select.h"
 #include "wave_ops.h"
 
@@ -283,15 +286,15 @@ __device__ __forceinline__ void slot_feature_grads(const GView& v, const GGrad& 
   }
 }
 
-// Selections without a slot, for the wave's pixels: dots (into s_d) and
-// feature gradients (to global memory), one selection at a time over the
-// wave's lanes.
-template <int DT>
+// Selections without a slot, for the wave's pixels, one selection at a time
+// over the wave's lanes. DOTS = false: feature gradients w g / Z added to
+// global memory (reads the weights); DOTS = true: the dots <g, f_j>, written
+// over the weight of the same selection (s_d aliases s_sel_w).
+template <int DT, bool DOTS>
 __device__ __forceinline__ void slotless(const GView& v, const GGrad& gg, const BwdLds& B,
                                          const int* __restrict__ s_sel_pos,
-                                         const float* __restrict__ s_sel_w, bool geo, int tx,
-                                         int ty, int wave, int lane, int dim, int ns,
-                                         float* __restrict__ s_d, int KP) {
+                                         float* __restrict__ s_sel_w, int tx, int ty, int wave,
+                                         int lane, int dim, int ns, int KP) {
   const int p_own = wave * 64 + lane;
   const int nfree = ns - __popc(B.smask[p_own]);  // slotted selections come first
   uint64_t todo = __ballot(nfree > 0);
@@ -306,37 +309,40 @@ __device__ __forceinline__ void slotless(const GView& v, const GGrad& gg, const 
     for (int j = j0; j < n; ++j) {
       const int pos = __builtin_amdgcn_readfirstlane(s_sel_pos[p * KP + j]);
       const int g = static_cast<int>(__builtin_amdgcn_readfirstlane(v.sorted_gid[pos]));
-      const float w = s_sel_w[p * KP + j] * inv;
-      float dot = 0.f;
-      for (int c = 4 * lane; c < dim; c += 256) {
-        const f32x4 gx = *reinterpret_cast<const QR_GLOBAL f32x4*>(grow + c);
-        if (geo) {
+      if constexpr (DOTS) {
+        float dot = 0.f;
+        for (int c = 4 * lane; c < dim; c += 256) {
+          const f32x4 gx = *reinterpret_cast<const QR_GLOBAL f32x4*>(grow + c);
           const float4 f = load_feat4_global<DT>(v.feats, v.scale, g, dim, c);
           dot += gx.x * f.x + gx.y * f.y + gx.z * f.z + gx.w * f.w;
         }
-        if (gg.grad_features) {
-          QR_GLOBAL float* dst = gg.grad_features + static_cast<int64_t>(g) * dim + c;
-          atomic_add(dst + 0, w * gx.x);
-          atomic_add(dst + 1, w * gx.y);
-          atomic_add(dst + 2, w * gx.z);
-          atomic_add(dst + 3, w * gx.w);
-        }
-      }
-      if (geo) {
         const float t = wave_sum(dot);
-        if (lane == 0) s_d[p * KP + j] = t;
+        if (lane == 0) s_sel_w[p * KP + j] = t;
+      } else {
+        const float w = s_sel_w[p * KP + j] * inv;
+        QR_GLOBAL float* dst = gg.grad_features + static_cast<int64_t>(g) * dim;
+        for (int c = 4 * lane; c < dim; c += 256) {
+          const f32x4 gx = *reinterpret_cast<const QR_GLOBAL f32x4*>(grow + c);
+          atomic_add(dst + c + 0, w * gx.x);
+          atomic_add(dst + c + 1, w * gx.y);
+          atomic_add(dst + c + 2, w * gx.z);
+          atomic_add(dst + c + 3, w * gx.w);
+        }
       }
     }
   }
 }
 
-// Backward of one tile (all 256 threads of the workgroup).
+// Backward of one tile (all 256 threads of the workgroup). Per-pixel LDS:
+// the walk's selected positions and weights ([256][KP] each); once the
+// feature gradients (which read the weights) are done, the dots d_j are
+// written over the weights, and the sweep recomputes each weight and T^Q_j
+// from the records with the walk's own float operations.
 template <int DT>
 __device__ __forceinline__ void quantile_backward_tile(const GView& v, const GGrad& gg, int tile,
                                                        int K, int dim, const qr_params& prm,
                                                        BwdLds& B, int* __restrict__ s_sel_pos,
-                                                       float* __restrict__ s_sel_w,
-                                                       float* __restrict__ s_d) {
+                                                       float* __restrict__ s_sel_w) {
   const int tiles_x = (v.W + kTile - 1) / kTile;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -352,7 +358,6 @@ __device__ __forceinline__ void quantile_backward_tile(const GView& v, const GGr
   const PixelSel sel = quantile_walk<QR_SELECT_QUANTILE>(v, lo, hi, K, pxc, pyc, inside, prm, B, s_sel_pos, s_sel_w, KP);
   const int ns = sel.ns;
   const int* my_pos = s_sel_pos + tid * KP;
-  const float* my_w = s_sel_w + tid * KP;
   const bool geo = gg.grad_means2d || gg.grad_co;
 
   // ---- slots: the tile's distinct selected positions, in list order ----
@@ -389,66 +394,83 @@ __device__ __forceinline__ void quantile_backward_tile(const GView& v, const GGr
   __syncthreads();
   const int nslot = B.nslot;
 
-  if (geo) {
-    // ---- dots d_pj (wave-local) ----
-    if (nslot > 0) slot_dots<DT>(v, gg, B, nslot, tx, ty, wave, lane, dim, s_d, KP);
-    slotless<DT>(v, gg, B, s_sel_pos, s_sel_w, true, tx, ty, wave, lane, dim, ns, s_d, KP);
-    wave_lds_sync();
+  if (gg.grad_features) {
+    // ---- feature gradients (read every pixel's weights) ----
+    if (nslot > 0) slot_feature_grads(v, gg, B, s_sel_w, nslot, tx, ty, wave, lane, dim, KP);
+    slotless<DT, false>(v, gg, B, s_sel_pos, s_sel_w, tx, ty, wave, lane, dim, ns, KP);
+  }
+  if (!geo) return;
+  __syncthreads();  // every wave is done with the weights before they are overwritten
 
-    // ---- reverse sweep over this pixel's selections ----
-    if (ns > 0) {
-      const float TQ = sel.TQ;
-      const float invZ = 1.f / (1.f - TQ);
-      const float* my_d = s_d + tid * KP;
-      float gout = 0.f;  // <g, out>
-      for (int j = 0; j < ns; ++j) gout += my_w[j] * my_d[j];
-      gout *= invZ;
-      float S = 0.f;
-      for (int j = ns - 1; j >= 0; --j) {
+  // ---- dots d_pj, written over the weights (wave-local) ----
+  float* s_d = s_sel_w;
+  if (nslot > 0) slot_dots<DT>(v, gg, B, nslot, tx, ty, wave, lane, dim, s_d, KP);
+  slotless<DT, true>(v, gg, B, s_sel_pos, s_sel_w, tx, ty, wave, lane, dim, ns, KP);
+  wave_lds_sync();
+
+  // ---- sweep over this pixel's selections ----
+  // Weights and T^Q_j are recomputed front to back exactly as the walk formed
+  // them; the tail sums S_j = sum_{l > j} w_l d_l are taken as the total
+  // minus the running prefix, both in double.
+  if (ns > 0) {
+    const float TQ = sel.TQ;
+    const float invZ = 1.f / (1.f - TQ);
+    const float* my_d = s_d + tid * KP;
+    double tot = 0.0;
+    {
+      float tq = 1.f;
+      for (int j = 0; j < ns; ++j) {
         const int g = static_cast<int>(v.sorted_gid[my_pos[j]]);
         const f32x2 m = v.means2d[g];
         const f32x4 c = v.conic_opacity[g];
-        const AlphaEval e = eval_alpha(make_float2(m.x, m.y), make_float4(c.x, c.y, c.z, c.w), pxc,
-                                       pyc, prm.alpha_max);
-        const float wj = my_w[j], dj = my_d[j];
-        const float tq = wj / e.alpha;  // T^Q before this selection
-        const float dL_da = invZ * (tq * dj - (S + gout * TQ) / (1.f - e.alpha));
-        S += wj * dj;
-        if (e.clamped || dL_da == 0.f) continue;
-        const float dpow = dL_da * e.alpha;
-        const float gv[kGeo] = {dpow * (-0.5f * e.dx * e.dx), dpow * (-e.dx * e.dy),
-                                dpow * (-0.5f * e.dy * e.dy), dL_da * e.G,
-                                dpow * (c.x * e.dx + c.y * e.dy), dpow * (c.y * e.dx + c.z * e.dy)};
-        const int s = slot_of(B, my_pos[j] - lo);
-        if (s >= 0) {
-#pragma unroll
-          for (int i = 0; i < kGeo; ++i) atomicAdd(&B.geo[wave][s * kGeo + i], gv[i]);
-        } else {
-          if (gg.grad_co)
-            for (int i = 0; i < 4; ++i) atomic_add(gg.grad_co + 4 * g + i, gv[i]);
-          if (gg.grad_means2d)
-            for (int i = 0; i < 2; ++i) atomic_add(gg.grad_means2d + 2 * g + i, gv[4 + i]);
-        }
+        const float a = gauss_alpha(make_float2(m.x, m.y), make_float4(c.x, c.y, c.z, c.w), pxc, pyc,
+                                    prm.alpha_max);
+        tot += static_cast<double>(tq * a) * my_d[j];
+        tq = tq * (1.f - a);
       }
     }
-    __syncthreads();
-    for (int i = tid; i < nslot * kGeo; i += kTilePix) {
-      const float val = B.geo[0][i] + B.geo[1][i] + B.geo[2][i] + B.geo[3][i];
-      const int s = i / kGeo, k = i - s * kGeo;
-      const int g = B.sgid[s];
-      if (val == 0.f) continue;
-      if (k < 4) {
-        if (gg.grad_co) atomic_add(gg.grad_co + 4 * g + k, val);
-      } else if (gg.grad_means2d) {
-        atomic_add(gg.grad_means2d + 2 * g + (k - 4), val);
+    const float gout = static_cast<float>(tot) * invZ;  // <g, out>
+    float tq = 1.f;
+    double pre = 0.0;
+    for (int j = 0; j < ns; ++j) {
+      const int g = static_cast<int>(v.sorted_gid[my_pos[j]]);
+      const f32x2 m = v.means2d[g];
+      const f32x4 c = v.conic_opacity[g];
+      const AlphaEval e = eval_alpha(make_float2(m.x, m.y), make_float4(c.x, c.y, c.z, c.w), pxc,
+                                     pyc, prm.alpha_max);
+      const float wj = tq * e.alpha, dj = my_d[j];
+      pre += static_cast<double>(wj) * dj;
+      const float S = static_cast<float>(tot - pre);  // sum over the later selections
+      const float dL_da = invZ * (tq * dj - (S + gout * TQ) / (1.f - e.alpha));
+      tq = tq * (1.f - e.alpha);
+      if (e.clamped || dL_da == 0.f) continue;
+      const float dpow = dL_da * e.alpha;
+      const float gv[kGeo] = {dpow * (-0.5f * e.dx * e.dx), dpow * (-e.dx * e.dy),
+                              dpow * (-0.5f * e.dy * e.dy), dL_da * e.G,
+                              dpow * (c.x * e.dx + c.y * e.dy), dpow * (c.y * e.dx + c.z * e.dy)};
+      const int s = slot_of(B, my_pos[j] - lo);
+      if (s >= 0) {
+#pragma unroll
+        for (int i = 0; i < kGeo; ++i) atomicAdd(&B.geo[wave][s * kGeo + i], gv[i]);
+      } else {
+        if (gg.grad_co)
+          for (int i = 0; i < 4; ++i) atomic_add(gg.grad_co + 4 * g + i, gv[i]);
+        if (gg.grad_means2d)
+          for (int i = 0; i < 2; ++i) atomic_add(gg.grad_means2d + 2 * g + i, gv[4 + i]);
       }
     }
   }
-
-  if (gg.grad_features) {
-    // ---- feature gradients ----
-    if (nslot > 0) slot_feature_grads(v, gg, B, s_sel_w, nslot, tx, ty, wave, lane, dim, KP);
-    if (!geo) slotless<DT>(v, gg, B, s_sel_pos, s_sel_w, false, tx, ty, wave, lane, dim, ns, s_d, KP);
+  __syncthreads();
+  for (int i = tid; i < nslot * kGeo; i += kTilePix) {
+    const float val = B.geo[0][i] + B.geo[1][i] + B.geo[2][i] + B.geo[3][i];
+    const int s = i / kGeo, k = i - s * kGeo;
+    const int g = B.sgid[s];
+    if (val == 0.f) continue;
+    if (k < 4) {
+      if (gg.grad_co) atomic_add(gg.grad_co + 4 * g + k, val);
+    } else if (gg.grad_means2d) {
+      atomic_add(gg.grad_means2d + 2 * g + (k - 4), val);
+    }
   }
 }
 
@@ -465,9 +487,8 @@ quantile_backward_kernel(ViewArgs v, GradPtrs gp, int n_tiles, qr_params prm, in
   const size_t n = bwd_sel_floats(K);
   int* s_sel_pos = reinterpret_cast<int*>(dyn_lds);
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + n;
-  float* s_d = s_sel_w + n;
   quantile_backward_tile<DT>(to_global(v), to_global(gp), xcd_remap(blockIdx.x, n_tiles), K, dim,
-                             prm, B, s_sel_pos, s_sel_w, s_d);
+                             prm, B, s_sel_pos, s_sel_w);
 }
 
 __device__ __forceinline__ GradPtrs grad_ptrs(const qr_view_grad& g) {
@@ -487,12 +508,11 @@ quantile_backward_batched_grid_kernel(const qr_view* __restrict__ views,
   const size_t n = bwd_sel_floats(K);
   int* s_sel_pos = reinterpret_cast<int*>(dyn_lds);
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + n;
-  float* s_d = s_sel_w + n;
   const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[xcd_remap(blockIdx.x, n_items)]);
   const uint32_t vi = packed >> kViewShift;
   quantile_backward_tile<DT>(to_global(view_args(views[vi])), to_global(grad_ptrs(grads[vi])),
                              static_cast<int>(packed & kTileMask), K, dim, prm, B, s_sel_pos,
-                             s_sel_w, s_d);
+                             s_sel_w);
 }
 
 // Many views in one persistent launch: items are taken from per-XCD ranges
@@ -515,7 +535,6 @@ quantile_backward_batched_kernel(const qr_view* __restrict__ views,
   const size_t n = bwd_sel_floats(K);
   int* s_sel_pos = reinterpret_cast<int*>(dyn_lds);
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + n;
-  float* s_d = s_sel_w + n;
   const int home = static_cast<int>(blockIdx.x % kBwdXcdQueues);
   // the item word alternates as in the forward: a wave running ahead writes
   // the other word
@@ -541,7 +560,7 @@ quantile_backward_batched_kernel(const qr_view* __restrict__ views,
     const uint32_t vi = packed >> kViewShift;
     quantile_backward_tile<DT>(to_global(view_args(views[vi])), to_global(grad_ptrs(grads[vi])),
                                static_cast<int>(packed & kTileMask), K, dim, prm, B, s_sel_pos,
-                               s_sel_w, s_d);
+                               s_sel_w);
   }
 }
 
@@ -550,7 +569,7 @@ __global__ void reset_bwd_counter_kernel(uint32_t* __restrict__ c) {
 }
 
 inline size_t bwd_dynamic_lds(int K) {
-  return static_cast<size_t>(kTilePix) * ((K + 3) & ~3) * 3 * sizeof(float);
+  return static_cast<size_t>(kTilePix) * ((K + 3) & ~3) * 2 * sizeof(float);
 }
 
 }  // namespace qr

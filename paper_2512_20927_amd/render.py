@@ -166,7 +166,9 @@ def bin_sort(pr: Projected, width: int, height: int, capacity: int | None = None
 def render_quantile(pr: Projected, bins: Bins, features, width: int, height: int, K: int,
                     params: RenderParams = RenderParams(), feature_scale=None, out=None,
                     debug: bool = False, stream=None):
-    """Quantile Rendering of one view. Returns dict(out, T_q, n_sel[, sel_gid, sel_w])."""
+    """Quantile Rendering of one view. Returns dict(out, T_q, n_sel[, T_final,
+    last_pos, sel_gid, sel_w]); with ``debug`` the selections and, for
+    Algorithm 1's rule, T_final and last_pos are returned too."""
     dev = features.device
     dim = features.shape[1]
     if out is None:
@@ -174,16 +176,21 @@ def render_quantile(pr: Projected, bins: Bins, features, width: int, height: int
         out = torch.empty(height, width, dim, dtype=out_t, device=dev)
     T_q = torch.empty(height, width, dtype=torch.float32, device=dev)
     n_sel = torch.empty(height, width, dtype=torch.int32, device=dev)
-    sel_gid = sel_w = None
+    sel_gid = sel_w = T_final = last_pos = None
     if debug:
         sel_gid = torch.empty(height, width, K, dtype=torch.int32, device=dev)
         sel_w = torch.empty(height, width, K, dtype=torch.float32, device=dev)
+        if params.selection == L.QR_SELECT_QUANTILE:
+            T_final = torch.empty(height, width, dtype=torch.float32, device=dev)
+            last_pos = torch.empty(height, width, dtype=torch.int32, device=dev)
     L.qr_render_quantile(width, height, params.c(), K, bins.tile_offsets, bins.sorted_gid,
                          pr.means2d, pr.conic_opacity, features, feature_scale, out, T_q, n_sel,
-                         sel_gid, sel_w, stream=stream)
+                         sel_gid, sel_w, stream=stream, T_final=T_final, last_pos=last_pos)
     r = dict(out=out, T_q=T_q, n_sel=n_sel)
     if debug:
         r.update(sel_gid=sel_gid, sel_w=sel_w)
+        if T_final is not None:
+            r.update(T_final=T_final, last_pos=last_pos)
     return r
 
 

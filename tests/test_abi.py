@@ -87,11 +87,15 @@ def test_render_validation(L):
     prm = L.make_params()
     d = ctypes.c_void_p(0x1000)
     P = ctypes.byref(prm)
-    q = lambda W, H, K, dt, sc, dim, sg=None, sw=None: lib.qr_render_quantile(
-        None, W, H, P, K, d, d, d, d, d, dt, sc, dim, d, None, None, sg, sw)
+    q = lambda W, H, K, dt, sc, dim, sg=None, sw=None, tf=None, lp=None, prm=P: lib.qr_render_quantile(
+        None, W, H, prm, K, d, d, d, d, d, dt, sc, dim, d, None, None, tf, lp, sg, sw)
     assert q(0, 64, 8, 0, None, 16) == L.QR_ERR_INVALID_ARG
     assert q(64, 64, 0, 0, None, 16) == L.QR_ERR_UNSUPPORTED
-    assert q(64, 64, 33, 0, None, 16) == L.QR_ERR_UNSUPPORTED
+    assert q(64, 64, L.QR_MAX_K + 1, 0, None, 16) == L.QR_ERR_UNSUPPORTED
+    # T_final / last_pos are Algorithm 1's outputs only
+    strat_p = ctypes.byref(L.make_params(selection=L.QR_SELECT_STRATIFIED))
+    assert q(64, 64, 8, 0, None, 16, tf=d, prm=strat_p) == L.QR_ERR_UNSUPPORTED
+    assert q(64, 64, 8, 0, None, 16, lp=d, prm=strat_p) == L.QR_ERR_UNSUPPORTED
     assert q(64, 64, 8, 0, None, 24) == L.QR_ERR_UNSUPPORTED
     assert q(64, 64, 8, 0, None, 0) == L.QR_ERR_UNSUPPORTED
     assert q(64, 64, 8, 7, None, 16) == L.QR_ERR_UNSUPPORTED
@@ -103,12 +107,13 @@ def test_render_validation(L):
     assert rc == L.QR_ERR_INVALID_ARG
     rc = lib.qr_render_dense_backward(None, 64, 64, P, d, d, d, d, d, 0, None, 20, d, d, d, d, d)
     assert rc == L.QR_ERR_UNSUPPORTED
-    rc = lib.qr_render_quantile_backward(None, 64, 64, P, 40, d, d, d, d, d, 0, None, 16, d, d, d, d)
+    rc = lib.qr_render_quantile_backward(None, 64, 64, P, L.QR_MAX_K + 1, d, d, d, d, d, 0, None, 16, d,
+                                         d, d, d)
     assert rc == L.QR_ERR_UNSUPPORTED
     # output dtype: bf16 maps from Q-Render only; unknown codes rejected
     bad_out = L.make_params(out_dtype=7)
     rc = lib.qr_render_quantile(None, 64, 64, ctypes.byref(bad_out), 8, d, d, d, d, d, 0, None, 16, d,
-                                None, None, None, None)
+                                None, None, None, None, None, None)
     assert rc == L.QR_ERR_UNSUPPORTED and "output dtype" in L.last_error()
     bf_out = L.make_params(out_dtype=L.QR_BF16)
     rc = lib.qr_render_dense(None, 64, 64, ctypes.byref(bf_out), d, d, d, d, d, 0, None, 16, d, None, None)
@@ -117,7 +122,7 @@ def test_render_validation(L):
     assert rc == L.QR_ERR_UNSUPPORTED
     bad_sel = L.make_params(selection=5)
     rc = lib.qr_render_quantile(None, 64, 64, ctypes.byref(bad_sel), 8, d, d, d, d, d, 0, None, 16, d,
-                                None, None, None, None)
+                                None, None, None, None, None, None)
     assert rc == L.QR_ERR_UNSUPPORTED and "selection" in L.last_error()
     rc = lib.qr_render_quantile_batched(None, 1, d, ctypes.byref(bad_sel), 8, 0, 16, d, 10, 0, None, 0)
     assert rc == L.QR_ERR_UNSUPPORTED
@@ -160,7 +165,7 @@ def test_batched_validation(L):
     assert bb(1, 10, -1, None, 0) == L.QR_ERR_INVALID_ARG
     assert bb(1, 10, 4, d, 16) == L.QR_ERR_CAPACITY
     assert bb(1, 1 << 31, 0, None, 0) == L.QR_ERR_INVALID_ARG
-    assert bb(1, 10, 0, None, 0, K=33) == L.QR_ERR_UNSUPPORTED
+    assert bb(1, 10, 0, None, 0, K=L.QR_MAX_K + 1) == L.QR_ERR_UNSUPPORTED
     assert bb(1, 10, 0, None, 0, dtype=9) == L.QR_ERR_UNSUPPORTED
     assert bb(1, 10, 0, None, 0, dim=24) == L.QR_ERR_UNSUPPORTED
     assert bb(1, 0, 0, None, 0) == L.QR_OK

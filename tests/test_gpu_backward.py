@@ -5,8 +5,19 @@ central finite differences.
 The oracle is fed the GPU's projected float32 records and bins. Pixels with a
 discrete decision within 1e-4 (relative) of its boundary may select or blend
 differently in float32; their incoming gradient is set to zero on both sides
-so that they do not enter the comparison. Tolerance: relative L2 error per
-gradient group <= 1e-3 (float32 kernel with atomics vs float64).
+so that they do not enter the comparison.
+
+Element-wise bound: every gradient entry must satisfy
+|gpu - oracle| <= ELEM_RTOL * m, with m the oracle's magnitude of the terms
+that form the entry (oracle.backward, magnitude=True). The kernels' products
+split float32 operands into bfloat16 pairs (relative error at most 3 * 2^-16
+= 4.6e-5 per product) and alpha' carries a few float32 ulps times |power|
+(about 2e-6 at the footprint edge); ELEM_RTOL = 2e-4 leaves a factor of three
+over their sum. Group norms: relative L2 error <= 1e-3 for every group whose
+gradient does not cancel (norm >= 1e-2 of its magnitude); a cancelling group
+(e.g. K = 1, where one selected Gaussian renders its own feature whatever its
+opacity and the geometric gradients vanish) is held to the element-wise
+bound only.
 """
 
 import numpy as np
@@ -20,6 +31,7 @@ from tests.parity_util import DECISION_WINDOW, proj_for_oracle
 pytestmark = pytest.mark.gpu
 
 GRAD_TOL = 1e-3
+ELEM_RTOL = 2e-4
 
 
 @pytest.fixture(scope="module")
@@ -61,19 +73,26 @@ GROUPS = (("features", "gf", "features", None), ("means2d", "gm", "means2d", Non
           ("conic", "gc", "conic", slice(0, 3)), ("opacity", "gc", "opacity", 3))
 
 
-def _compare(gpu, orc, floors=None, n_active_min=10):
-    """Relative L2 error per group. `floors` (per group) keeps the denominator
-    away from zero where the exact gradient cancels (e.g. K = 1: one selected
-    Gaussian renders its own feature whatever its opacity)."""
+def _compare(gpu, orc, n_active_min=10):
+    """Element-wise bound against the term magnitudes, and relative L2 error
+    per non-cancelling group (module doc). `orc` comes from the oracle with
+    magnitude=True."""
     stats = {}
     for name, gk, ok, sl in GROUPS:
-        g = gpu[gk] if sl is None else gpu[gk][:, sl]
+        g = np.asarray(gpu[gk] if sl is None else gpu[gk][:, sl], np.float64)
         o = np.asarray(orc[ok], np.float64)
-        den = max(np.linalg.norm(o), (floors or {}).get(name, 0.0), 1e-30)
-        stats[name] = float(np.linalg.norm(np.asarray(g, np.float64) - o) / den)
-    print("gradient rel L2 errors", stats)
-    for k, v in stats.items():
-        assert v <= GRAD_TOL, (k, stats)
+        m = np.asarray(orc["abs"][ok], np.float64)
+        excess = np.abs(g - o) - ELEM_RTOL * m
+        worst = float(excess.max())
+        rel_elem = float((np.abs(g - o) / np.maximum(m, 1e-300)).max())
+        assert worst <= 0.0, (name, "element-wise", rel_elem)
+        no, nm = np.linalg.norm(o), np.linalg.norm(m)
+        cancelling = no < 1e-2 * nm
+        rel = float(np.linalg.norm(g - o) / max(no, 1e-300))
+        stats[name] = dict(rel_l2=rel, max_err_over_magnitude=rel_elem, cancelling=bool(cancelling))
+        if not cancelling:
+            assert rel <= GRAD_TOL, (name, stats[name])
+    print("gradient errors", stats)
     assert np.count_nonzero(np.abs(orc["features"]).sum(1) > 0) >= n_active_min
     return stats
 
@@ -84,7 +103,7 @@ def _run(qr, sc, cam, K, storage="f32", seed=0):
     proj = proj_for_oracle(host["pr"])
     rng = np.random.default_rng(seed)
     gout = rng.standard_normal((H, W, sc.dim))
-    results, floors = {}, None
+    results = {}
     for kind in ("dense", "quantile"):
         if kind == "quantile":
             fw = oracle.render_quantile(proj, host["gids"], host["offs"], dec, W, H, K)
@@ -100,20 +119,16 @@ def _run(qr, sc, cam, K, storage="f32", seed=0):
             qr._lib.qr_render_quantile_backward(W, H, qr.RenderParams().c(), K, bins.tile_offsets,
                                                 bins.sorted_gid, pr.means2d, pr.conic_opacity, feats,
                                                 scale, g_t, gf, gm, gc)
-            orc = oracle.quantile_backward(proj, host["gids"], host["offs"], dec, W, H, K, g)
+            orc = oracle.quantile_backward(proj, host["gids"], host["offs"], dec, W, H, K, g, magnitude=True)
         else:
             out = qr.render_dense(pr, bins, feats, W, H, feature_scale=scale)["out"]
             qr._lib.qr_render_dense_backward(W, H, qr.RenderParams().c(), bins.tile_offsets,
                                              bins.sorted_gid, pr.means2d, pr.conic_opacity, feats,
                                              scale, out, g_t, gf, gm, gc)
-            orc = oracle.dense_backward(proj, host["gids"], host["offs"], dec, W, H, g)
+            orc = oracle.dense_backward(proj, host["gids"], host["offs"], dec, W, H, g, magnitude=True)
         torch.cuda.synchronize()
         gpu = dict(gf=gf.cpu().numpy(), gm=gm.cpu().numpy(), gc=gc.cpu().numpy())
-        results[kind] = _compare(gpu, orc, floors)
-        if kind == "dense":
-            # 1% of the dense gradient's norm: the scale of a non-cancelling sum
-            floors = {name: 1e-2 * float(np.linalg.norm(np.asarray(orc[ok])[:, sl] if sl is not None and np.asarray(orc[ok]).ndim > 1 else np.asarray(orc[ok])))
-                      for name, _, ok, sl in GROUPS}
+        results[kind] = _compare(gpu, orc)
     return results
 
 
@@ -123,8 +138,10 @@ def test_backward_fd_subcase(qr):
     _run(qr, sc, cam, 8)
 
 
-@pytest.mark.parametrize("K", [1, 4, 16, 32])
+@pytest.mark.parametrize("K", [1, 4, 16, 32, 40, 50, 64])
 def test_backward_ragged_small_dim(qr, K):
+    """K = 40 (the paper's trained setting), 50 and 64 keep up to 64
+    selections per pixel in LDS."""
     sc = synth.make_tiny(3, n=1500, dim=16)
     cam = synth.tiny_camera(48)
     cam.height, cam.cy = 40, 20.0
@@ -193,9 +210,9 @@ def test_autograd_function_cosine_loss(qr):
         (((1 - cos2) * mask).sum() / mask.sum()).backward()
         g = out_d.grad.double().cpu().numpy()
         if kind == "quantile":
-            orc = oracle.quantile_backward(proj, host["gids"], host["offs"], dec, W, H, K, g)
+            orc = oracle.quantile_backward(proj, host["gids"], host["offs"], dec, W, H, K, g, magnitude=True)
         else:
-            orc = oracle.dense_backward(proj, host["gids"], host["offs"], dec, W, H, g)
+            orc = oracle.dense_backward(proj, host["gids"], host["offs"], dec, W, H, g, magnitude=True)
         gpu = dict(gf=f.grad.cpu().numpy(), gm=m2.grad.cpu().numpy(), gc=co.grad.cpu().numpy())
         _compare(gpu, orc)
 
@@ -228,6 +245,7 @@ def test_backward_diff_config_full_size_sampled_tiles(qr):
     qr._lib.qr_render_quantile_backward(W, H, qr.RenderParams().c(), K, bins.tile_offsets, bins.sorted_gid,
                                         pr.means2d, pr.conic_opacity, feats, scale,
                                         _t(g.astype(np.float32)), gf, gm, gc)
-    orc = oracle.quantile_backward(proj, host["gids"], host["offs"], dec, W, H, K, g, tiles=tiles)
+    orc = oracle.quantile_backward(proj, host["gids"], host["offs"], dec, W, H, K, g, tiles=tiles,
+                                   magnitude=True)
     torch.cuda.synchronize()
     _compare(dict(gf=gf.cpu().numpy(), gm=gm.cpu().numpy(), gc=gc.cpu().numpy()), orc)
