@@ -254,6 +254,31 @@ int qr_bin_sort(void* stream, int64_t n, int32_t tiles_x, int32_t tiles_y,
                 uint32_t* tile_offsets, uint32_t* total_pairs);
 
 /*
+ * qr_bin_sort_noalloc - qr_bin_sort with no workspace argument, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the workspace is a static
+ * device array of QR_BIN_SORT_SCRATCH_BYTES, one copy per GPU, which each GPU
+ * holds from the library's first use on it until the process ends. The call
+ * itself allocates and frees nothing; the caller still passes inputs and
+ * outputs as for qr_bin_sort, and the stream must belong to the current
+ * device. Results are identical to qr_bin_sort's.
+ * Every call on one GPU shares that GPU's array (the call clears what must
+ * start at zero with a kernel on `stream`), so calls that overlap on one GPU
+ * (different streams, or threads without ordering) race and must not be
+ * made.
+ * Errors: as qr_bin_sort, and QR_ERR_CAPACITY when the workspace that
+ * qr_bin_sort_workspace_size gives for (n, tiles_x, tiles_y, capacity)
+ * exceeds QR_BIN_SORT_SCRATCH_BYTES (nothing launched): about 4 million pairs
+ * at frame-sized tile grids.
+ */
+#define QR_BIN_SORT_SCRATCH_BYTES 67108864 /* 64 MiB */
+int qr_bin_sort_noalloc(void* stream, int64_t n, int32_t tiles_x, int32_t tiles_y,
+                        const int32_t* tile_rect, const uint32_t* tiles_touched,
+                        const float* depth, int64_t capacity,
+                        uint32_t* sorted_gid, uint64_t* sorted_keys,
+                        uint32_t* tile_offsets, uint32_t* total_pairs);
+
+/*
  * qr_bin_sort_views - qr_bin_sort of a batch of views in one launch
  * sequence: the records are n_views blocks of n_per_view (as written by
  * qr_project_views), and view v's tiles_x x tiles_y grid takes tile ids

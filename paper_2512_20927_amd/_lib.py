@@ -25,6 +25,7 @@ QR_SELECT_QUANTILE, QR_SELECT_STRATIFIED, QR_SELECT_TOPK = 0, 1, 2
 QR_REDUCE_MAX, QR_REDUCE_MEAN = 0, 1
 QR_TILE = 16
 QR_MAX_K = 64
+QR_BIN_SORT_SCRATCH_BYTES = 64 * 1024 * 1024
 
 EXPORTED = [
     "qr_version", "qr_last_error", "qr_project", "qr_count_pairs",
@@ -32,7 +33,7 @@ EXPORTED = [
     "qr_render_dense_backward", "qr_render_quantile_backward", "qr_quantize_features",
     "qr_render_quantile_batched", "qr_batch_schedule", "qr_project_views", "qr_bin_sort_views",
     "qr_render_quantile_batched_backward", "qr_autotune_batched", "qr_devoxelize",
-    "qr_devoxelize_backward", "qr_sh_to_rgb", "qr_sh_to_rgb_views",
+    "qr_devoxelize_backward", "qr_sh_to_rgb", "qr_sh_to_rgb_views", "qr_bin_sort_noalloc",
 ]
 QR_BATCH_TILE_BITS = 20
 
@@ -85,6 +86,7 @@ def _load():
         "qr_count_pairs": ([P, i64, P, P, sz, ctypes.POINTER(ctypes.c_uint64)], i32),
         "qr_bin_sort_workspace_size": ([i64, i32, i32, i64, ctypes.POINTER(ctypes.c_size_t)], i32),
         "qr_bin_sort": ([P, i64, i32, i32, P, P, P, i64, P, sz, P, P, P, P], i32),
+        "qr_bin_sort_noalloc": ([P, i64, i32, i32, P, P, P, i64, P, P, P, P], i32),
         "qr_project_views": ([P, i64, P, P, P, P, i32, cam_p, prm_p, P, P, P, P, P], i32),
         "qr_bin_sort_views": ([P, i32, i64, i32, i32, P, P, P, i64, P, sz, P, P, P, P], i32),
         "qr_render_dense": ([P, i32, i32, prm_p, P, P, P, P, P, i32, P, i32, P, P, P], i32),
@@ -273,6 +275,22 @@ def qr_bin_sort(n, tiles_x, tiles_y, tile_rect, tiles_touched, depth, capacity, 
                             _ptr(tiles_touched), _ptr(depth), capacity, _ptr(workspace),
                             workspace.numel() * workspace.element_size(), _ptr(sorted_gid),
                             _ptr(sorted_keys), _ptr(tile_offsets), _ptr(total_pairs)))
+
+
+def qr_bin_sort_noalloc(n, tiles_x, tiles_y, tile_rect, tiles_touched, depth, capacity,
+                        sorted_gid, sorted_keys, tile_offsets, total_pairs, stream=None):
+    """qr_bin_sort with the library's static per-GPU workspace (no workspace
+    argument; calls on one GPU must not overlap)."""
+    _need(tile_rect, 4 * n, I32, "tile_rect")
+    _need(tiles_touched, n, I32, "tiles_touched")
+    _need(depth, n, F32, "depth")
+    _need(sorted_gid, capacity, I32, "sorted_gid")
+    _need(sorted_keys, capacity, (torch.int64,), "sorted_keys")
+    _need(tile_offsets, tiles_x * tiles_y + 1, I32, "tile_offsets")
+    _need(total_pairs, 1, I32, "total_pairs")
+    _check(_LIB.qr_bin_sort_noalloc(_stream(stream), n, tiles_x, tiles_y, _ptr(tile_rect),
+                                    _ptr(tiles_touched), _ptr(depth), capacity, _ptr(sorted_gid),
+                                    _ptr(sorted_keys), _ptr(tile_offsets), _ptr(total_pairs)))
 
 
 def qr_bin_sort_views(n_views, n_per_view, tiles_x, tiles_y, tile_rect, tiles_touched, depth,

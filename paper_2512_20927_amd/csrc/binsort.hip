@@ -14,11 +14,12 @@
 //      whatever order step 3 produced. Buckets of up to 256 keys are
 //      bitonic-sorted one key per thread (lane shuffles inside a wave, LDS
 //      across waves), up to kLdsItems in LDS; longer ones take a
-//      single-workgroup LSD radix sort through global scratch.
+//      single-workgroup LSD radix sort through a workspace segment.
 // Depth is positive (z > z_near > 0), so its IEEE bit pattern orders like
 // the value. No kernel synchronises with the host: grids are sized by the
 // caller's capacity and every kernel reads the pair count from device memory.
 #include <algorithm>
+#include <mutex>
 
 #include "common.h"
 
@@ -245,7 +246,7 @@ __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v,
 __global__ void __launch_bounds__(256)
 tile_sort_kernel(int n_tiles, const uint32_t* __restrict__ offsets, int64_t capacity,
                  int gid_bits, unsigned long long* __restrict__ bucket,
-                 unsigned long long* __restrict__ scratch, uint32_t* __restrict__ sorted_gid,
+                 unsigned long long* __restrict__ radix_tmp, uint32_t* __restrict__ sorted_gid,
                  unsigned long long* __restrict__ sorted_keys) {
   __shared__ unsigned long long s_key[kLdsItems];
   __shared__ uint32_t run[kRadix];
@@ -321,10 +322,10 @@ tile_sort_kernel(int n_tiles, const uint32_t* __restrict__ offsets, int64_t capa
   }
 
   // long bucket: LSD radix sort, one workgroup, ping-pong between the bucket
-  // and the scratch segment. Digits cover the id bits (0 .. gid_bits-1) and
+  // and the radix_tmp segment. Digits cover the id bits (0 .. gid_bits-1) and
   // the depth bits (32 .. 63); bits gid_bits .. 31 are zero in every key.
   unsigned long long* src = bucket + lo;
-  unsigned long long* dst = scratch + lo;
+  unsigned long long* dst = radix_tmp + lo;
   const int gid_passes = (gid_bits + 7) / 8;
   const int passes = gid_passes + 4;
   for (int p = 0; p < passes; ++p) {
@@ -356,7 +357,7 @@ tile_sort_kernel(int n_tiles, const uint32_t* __restrict__ offsets, int64_t capa
 
 // ---- workspace layout --------------------------------------------------------
 struct Layout {
-  size_t cnt, cursor, part, bucket, scratch, bytes;
+  size_t cnt, cursor, part, bucket, radix_tmp, bytes;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -368,7 +369,7 @@ static Layout layout(int64_t n_tiles, int64_t capacity) {
   L.cursor = o;  o = align256(o + sizeof(uint32_t) * (n_tiles + 1));
   L.part = o;    o = align256(o + sizeof(uint32_t) * (scan_parts(n_tiles) + 1));
   L.bucket = o;  o = align256(o + sizeof(uint64_t) * std::max<int64_t>(capacity, 1));
-  L.scratch = o; o = align256(o + sizeof(uint64_t) * std::max<int64_t>(capacity, 1));
+  L.radix_tmp = o; o = align256(o + sizeof(uint64_t) * std::max<int64_t>(capacity, 1));
   L.bytes = o;
   return L;
 }
@@ -422,7 +423,7 @@ static int bin_sort_impl(const char* name, void* stream, int64_t n_views, int64_
   auto* cursor = reinterpret_cast<uint32_t*>(ws + L.cursor);
   auto* part = reinterpret_cast<uint32_t*>(ws + L.part);
   auto* bucket = reinterpret_cast<unsigned long long*>(ws + L.bucket);
-  auto* scratch = reinterpret_cast<unsigned long long*>(ws + L.scratch);
+  auto* radix_tmp = reinterpret_cast<unsigned long long*>(ws + L.radix_tmp);
 
   // counters and cursors are adjacent in the layout: one fill clears both
   const int64_t zero_n = static_cast<int64_t>((L.part - L.cnt) / sizeof(uint32_t));
@@ -442,7 +443,7 @@ static int bin_sort_impl(const char* name, void* stream, int64_t n_views, int64_
   if (capacity > 0)
     hipLaunchKernelGGL(tile_sort_kernel, dim3(static_cast<unsigned>(n_tiles)), dim3(256), 0, s,
                        static_cast<int>(n_tiles), tile_offsets, capacity, bits_for(n_per_view), bucket,
-                       scratch, sorted_gid, reinterpret_cast<unsigned long long*>(sorted_keys));
+                       radix_tmp, sorted_gid, reinterpret_cast<unsigned long long*>(sorted_keys));
   return check_launch(name);
 }
 
@@ -456,6 +457,74 @@ extern "C" int qr_bin_sort(void* stream, int64_t n, int32_t tiles_x, int32_t til
   return bin_sort_impl("qr_bin_sort", stream, 1, n, tiles_x, tiles_y, tile_rect, tiles_touched,
                        depth, capacity, workspace, workspace_bytes, sorted_gid, sorted_keys,
                        tile_offsets, total_pairs);
+}
+
+// ---- zero-allocation variant ------------------------------------------------
+namespace qr {
+
+// The workspace of qr_bin_sort_noalloc: one copy per GPU, allocated when the
+// library's code object is loaded on that GPU and held until the process
+// ends. In host code `scratch` only names the symbol; its device address is
+// looked up once per device (hipGetSymbolAddress) and only that address is
+// passed to kernels.
+static __device__ __align__(256) unsigned char scratch[QR_BIN_SORT_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static void* g_scratch_addr[kMaxDevices];
+
+// Device address of `scratch` on the current device (looked up on the first
+// call for each device).
+static int scratch_address(const char* name, void** addr) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(QR_ERR_HIP, "%s: hipGetDevice: %s", name, hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(QR_ERR_UNSUPPORTED, "%s: device index %d beyond %d", name, dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(QR_ERR_HIP, "%s: hipGetSymbolAddress of the scratch array on device %d: %s",
+                  name, dev, hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+  }
+  *addr = g_scratch_addr[dev];
+  return QR_OK;
+}
+
+}  // namespace qr
+
+extern "C" int qr_bin_sort_noalloc(void* stream, int64_t n, int32_t tiles_x, int32_t tiles_y,
+                                   const int32_t* tile_rect, const uint32_t* tiles_touched,
+                                   const float* depth, int64_t capacity, uint32_t* sorted_gid,
+                                   uint64_t* sorted_keys, uint32_t* tile_offsets,
+                                   uint32_t* total_pairs) {
+  const char* name = "qr_bin_sort_noalloc";
+  if (n < 0 || capacity < 0 || tiles_x <= 0 || tiles_y <= 0)
+    return fail(QR_ERR_INVALID_ARG, "%s: bad sizes", name);
+  // checked before the layout is computed, so that the sizes below cannot
+  // overflow
+  if (capacity > static_cast<int64_t>(QR_BIN_SORT_SCRATCH_BYTES) ||
+      static_cast<int64_t>(tiles_x) * tiles_y > static_cast<int64_t>(QR_BIN_SORT_SCRATCH_BYTES))
+    return fail(QR_ERR_CAPACITY, "%s: capacity %lld pairs over %lld tiles exceeds the %d-byte scratch",
+                name, static_cast<long long>(capacity),
+                static_cast<long long>(tiles_x) * tiles_y, QR_BIN_SORT_SCRATCH_BYTES);
+  const size_t need = layout(static_cast<int64_t>(tiles_x) * tiles_y, capacity).bytes;
+  if (need > static_cast<size_t>(QR_BIN_SORT_SCRATCH_BYTES))
+    return fail(QR_ERR_CAPACITY,
+                "%s: capacity %lld pairs over %lld tiles needs %zu bytes of scratch, the maximum "
+                "is %d",
+                name, static_cast<long long>(capacity), static_cast<long long>(tiles_x) * tiles_y,
+                need, QR_BIN_SORT_SCRATCH_BYTES);
+  if (n >= (1ll << 32)) return fail(QR_ERR_UNSUPPORTED, "%s: n must be below 2^32 - 1", name);
+  void* ws = nullptr;
+  const int rc = scratch_address(name, &ws);
+  if (rc != QR_OK) return rc;
+  return bin_sort_impl(name, stream, 1, n, tiles_x, tiles_y, tile_rect, tiles_touched, depth,
+                       capacity, ws, static_cast<size_t>(QR_BIN_SORT_SCRATCH_BYTES), sorted_gid,
+                       sorted_keys, tile_offsets, total_pairs);
 }
 
 extern "C" int qr_bin_sort_views(void* stream, int32_t n_views, int64_t n_per_view,

@@ -82,6 +82,23 @@ def test_bin_sort_validation_and_workspace_size(L):
     assert rc == L.QR_ERR_UNSUPPORTED
 
 
+def test_bin_sort_noalloc_rejects_sizes_beyond_its_scratch(L):
+    """The static-workspace binning refuses, before touching a device, any
+    size whose workspace would not fit its fixed scratch array."""
+    lib = L.lib()
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    out = ctypes.c_size_t(0)
+    cap = 4_300_000
+    assert lib.qr_bin_sort_workspace_size(1000, 40, 30, cap, ctypes.byref(out)) == L.QR_OK
+    assert out.value > L.QR_BIN_SORT_SCRATCH_BYTES
+    rc = lib.qr_bin_sort_noalloc(None, 1000, 40, 30, dummy, dummy, dummy, cap, dummy, None, dummy, dummy)
+    assert rc == L.QR_ERR_CAPACITY and "scratch" in L.last_error()
+    rc = lib.qr_bin_sort_noalloc(None, 1000, 40, 30, dummy, dummy, dummy, 1 << 40, dummy, None, dummy, dummy)
+    assert rc == L.QR_ERR_CAPACITY
+    rc = lib.qr_bin_sort_noalloc(None, 1000, 0, 30, dummy, dummy, dummy, 100, dummy, None, dummy, dummy)
+    assert rc == L.QR_ERR_INVALID_ARG
+
+
 def test_render_validation(L):
     lib = L.lib()
     prm = L.make_params()
