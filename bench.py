@@ -77,18 +77,28 @@ class BatchState:
         self.outs, self.aux_f, self.aux_i = outs, aux_f, aux_i
         self.per_view = [self.vb.view(self.pv, v) for v in range(len(cams))]
         self.bq = self.make_bq(K)
+        self.bd = None
         self.front_done = torch.cuda.Event()
         self.render_done = torch.cuda.Event()
+
+    def _views(self, feats=None):
+        return [dict(tile_offsets=b.tile_offsets, sorted_gid=b.sorted_gid, means2d=pr.means2d,
+                     conic_opacity=pr.conic_opacity,
+                     features=self.s["feats"] if feats is None else feats[v],
+                     feature_scale=self.scale, out=self.outs[v], T_q=self.aux_f[v],
+                     n_sel=self.aux_i[v], width=self.W, height=self.H)
+                for v, (pr, b) in enumerate(self.per_view)]
 
     def make_bq(self, K):
         """A batched Q-Render launch over all views of this state for K."""
         from paper_2512_20927_amd.batched import BatchedQuantile
-        views = [dict(tile_offsets=b.tile_offsets, sorted_gid=b.sorted_gid, means2d=pr.means2d,
-                      conic_opacity=pr.conic_opacity, features=self.s["feats"],
-                      feature_scale=self.scale, out=self.outs[v], T_q=self.aux_f[v],
-                      n_sel=self.aux_i[v], width=self.W, height=self.H)
-                 for v, (pr, b) in enumerate(self.per_view)]
-        return BatchedQuantile(views, K, self.dim, self.dtype_code, self.prm)
+        return BatchedQuantile(self._views(), K, self.dim, self.dtype_code, self.prm)
+
+    def make_bd(self):
+        """The dense blend over the same views, items and launch shapes."""
+        from paper_2512_20927_amd.batched import BatchedDense
+        self.bd = BatchedDense(self._views(), self.dim, self.dtype_code, self.prm)
+        return self.bd
 
     def front(self):
         s, pv = self.s, self.pv
@@ -96,12 +106,6 @@ class BatchState:
                                 self.prm, pv.means2d, pv.conic_opacity, pv.depth, pv.tile_rect,
                                 pv.tiles_touched)
         self.vb(pv)
-
-    def render_dense(self):
-        for v, (pr, b) in enumerate(self.per_view):
-            self.L.qr_render_dense(self.W, self.H, self.prm, b.tile_offsets, b.sorted_gid, pr.means2d,
-                                   pr.conic_opacity, self.s["feats"], self.scale, self.outs[v],
-                                   self.aux_f[v], self.aux_i[v])
 
 
 
@@ -121,28 +125,24 @@ class RgbState(BatchState):
 
     def make_bq(self, K):
         from paper_2512_20927_amd.batched import BatchedQuantile
-        views = [dict(tile_offsets=b.tile_offsets, sorted_gid=b.sorted_gid, means2d=pr.means2d,
-                      conic_opacity=pr.conic_opacity, features=self.rgb[v], feature_scale=None,
-                      out=self.outs[v], T_q=self.aux_f[v], n_sel=self.aux_i[v], width=self.W,
-                      height=self.H)
-                 for v, (pr, b) in enumerate(self.per_view)]
-        return BatchedQuantile(views, K, 16, self.L.QR_F32, self.prm)
+        return BatchedQuantile(self._views(self.rgb), K, 16, self.L.QR_F32, self.prm)
+
+    def make_bd(self):
+        from paper_2512_20927_amd.batched import BatchedDense
+        self.bd = BatchedDense(self._views(self.rgb), 16, self.L.QR_F32, self.prm)
+        return self.bd
 
     def front(self):
         self.L.qr_sh_to_rgb_views(self.s["means"], self.sh, 3, self.cams_py, self.rgb_all)
         super().front()
 
-    def render_dense(self):
-        for v, (pr, b) in enumerate(self.per_view):
-            self.L.qr_render_dense(self.W, self.H, self.prm, b.tile_offsets, b.sorted_gid, pr.means2d,
-                                   pr.conic_opacity, self.rgb[v], None, self.outs[v], self.aux_f[v],
-                                   self.aux_i[v])
 
-def timed_batched(states, steps, warmup, schedule, wg_per_cu, overlap=True):
+def timed_batched(states, steps, warmup, schedule, wg_per_cu, overlap=True, dense=False):
     """`steps` steps of (front, batched render). With overlap, a software
     pipeline: the front of step i+1 runs on a side stream while step i's
     render runs on the main stream (the two BatchStates alternate); the timed
     region holds exactly `steps` fronts and `steps` renders either way.
+    dense: the batched dense blend (BatchState.bd) instead of Q-Render.
     Returns (seconds, mean batched-render ms from HIP events on the render
     stream)."""
     import torch
@@ -159,7 +159,8 @@ def timed_batched(states, steps, warmup, schedule, wg_per_cu, overlap=True):
             main.wait_event(X.front_done)
             # the start event follows the schedule build: the events bracket
             # the render launch itself
-            X.bq.render(schedule, wg_per_cu, start_event=evs[i][0] if evs is not None else None)
+            (X.bd if dense else X.bq).render(schedule, wg_per_cu,
+                                             start_event=evs[i][0] if evs is not None else None)
             if evs is not None:
                 evs[i][1].record(main)
             X.render_done.record(main)
@@ -180,19 +181,40 @@ def timed_batched(states, steps, warmup, schedule, wg_per_cu, overlap=True):
     return dt, float(np.mean([a.elapsed_time(b) for a, b in evs]))
 
 
-def timed_dense(state, steps, warmup):
-    """`steps` steps of (front, per-pose dense renders) on one stream."""
+def timed_dense(states, steps, warmup):
+    """The dense blend timed exactly as Q-Render: the batched launch over the
+    same (pose, tile) items, its launch shape autotuned, the front of the
+    next step overlapped (or not, whichever is faster). Returns (seconds,
+    render ms, tuned launch, (seconds sequential, seconds overlapped))."""
+    from paper_2512_20927_amd.batched import autotune
+    for st in states:
+        if st.bd is None:
+            st.make_bd()
+    tuned, _ = autotune(states[0].bd, wg_per_cu=(0, 2, 4), use_cache=False)
+    dt_seq, k_seq = timed_batched(states, steps, warmup, tuned["schedule"], tuned["wg_per_cu"],
+                                  overlap=False, dense=True)
+    dt_ovl, _ = timed_batched(states, steps, warmup, tuned["schedule"], tuned["wg_per_cu"],
+                              overlap=True, dense=True)
+    return min(dt_seq, dt_ovl), k_seq, tuned, (dt_seq, dt_ovl)
+
+
+def dense_list_prefix(b, n_contrib, W, H):
+    """(list entries up to each tile's last blended entry, distinct Gaussians
+    among them) of one view: the records and feature rows the dense blend
+    must read."""
     import torch
-    for _ in range(max(warmup, 1)):
-        state.front()
-        state.render_dense()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        state.front()
-        state.render_dense()
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0
+    tx, ty = (W + 15) // 16, (H + 15) // 16
+    nc = torch.zeros(ty * 16, tx * 16, dtype=torch.int64, device=n_contrib.device)
+    nc[:H, :W] = n_contrib.long()
+    m = nc.view(ty, 16, tx, 16).amax(dim=(1, 3)).reshape(-1)
+    lo = b.tile_offsets[:-1].long()
+    total = int(m.sum().item())
+    if total == 0:
+        return 0, 0
+    start = torch.repeat_interleave(lo, m)
+    first = torch.repeat_interleave(torch.cumsum(m, 0) - m, m)
+    idx = start + torch.arange(total, device=m.device) - first
+    return total, int(torch.unique(b.sorted_gid[idx]).numel())
 
 
 def measured_traffic(kernel, workload):
@@ -207,10 +229,60 @@ def measured_traffic(kernel, workload):
     return int(info["traffic_bytes_per_launch"])
 
 
-def cpu_reference(sc, cam, K, budget_s, gpu_out=None, gpu_bins=None):
-    """FP64 oracle pipeline on this host (1 thread): full projection and
-    binning, then Algorithm 1 on an evenly spaced sample of tiles until the
-    budget is used; frame time extrapolated to all tiles."""
+_CPU_SHARED = {}
+
+
+def _cpu_worker(tiles):
+    """One pool worker (forked: the inputs are inherited through
+    _CPU_SHARED): Algorithm 1 on its tiles with one BLAS thread."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    d = _CPU_SHARED
+    with threadpool_limits(1):
+        oracle.render_quantile(d["pr"], d["gids"], d["offs"], d["feats"], d["W"], d["H"], d["K"],
+                               tiles=tiles)
+    return len(tiles)
+
+
+def _host_cores():
+    """CPU threads this process may use, at most 16 (one GPU's share of the
+    host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _tile_err(gpu_map, ref, tiles, W, H):
+    """Per-pixel relative L2 error of a GPU map against an oracle result over
+    the given tiles: all pixels, and those whose decisions all lie more than
+    1e-4 (relative) from their boundaries."""
+    tx = (W + 15) // 16
+    errs, clean = [], []
+    for t in tiles:
+        y0, x0 = (t // tx) * 16, (t % tx) * 16
+        g = gpu_map[y0:y0 + 16, x0:x0 + 16].astype(np.float64)
+        r = ref["out"][y0:y0 + 16, x0:x0 + 16]
+        e = np.linalg.norm(g - r, axis=-1) / np.maximum(np.linalg.norm(r, axis=-1), 1e-6)
+        errs.append(e.ravel())
+        clean.append((ref["margin"][y0:y0 + 16, x0:x0 + 16] > 1e-4).ravel())
+    e, c = np.concatenate(errs), np.concatenate(clean)
+    return {"pixels": int(e.size), "max": float(e.max()), "p99": float(np.percentile(e, 99)),
+            "mean": float(e.mean()), "over_1e-2": int((e > 1e-2).sum()),
+            "max_clean": float(e[c].max()) if c.any() else 0.0, "clean": int(c.sum())}
+
+
+def cpu_reference(sc, cam, K, budget_s, gpu_q=None, gpu_d=None, label="room pose 100"):
+    """The FP64 oracle pipeline on this host: projection and binning of the
+    whole scene, then Algorithm 1 on an evenly spaced random sample of tiles
+    sized to the time budget, on one core and then split over a fork pool on
+    all host cores (at most 16); frame time extrapolated to all tiles.
+    With gpu_q / gpu_d (host copies of the GPU's timed Q-Render and dense
+    maps of this camera), the oracle's maps of the sampled tiles (and the
+    dense blend of a few of them) are compared with them: per-pixel relative
+    L2 error against the end-to-end FP64 pipeline."""
+    import multiprocessing as mp
     import oracle
     try:
         from threadpoolctl import threadpool_limits
@@ -237,17 +309,47 @@ def cpu_reference(sc, cam, K, budget_s, gpu_out=None, gpu_bins=None):
     per_tile = max(time.perf_counter() - t0 - t_alloc, 1e-6) / 4
     left = budget_s - t_proj - t_bin - 4 * per_tile
     n_s = int(min(n_tiles, max(8, left / max(per_tile, 1e-6))))
-    t0 = time.perf_counter()
-    oracle.render_quantile(pr, gids, offs, feats, cam.width, cam.height, K, tiles=order[:n_s])
-    t_render = time.perf_counter() - t0
     done = order[:n_s]
-    frame_s = t_proj + t_bin + t_render * n_tiles / len(done)
+    t0 = time.perf_counter()
+    ref_q = oracle.render_quantile(pr, gids, offs, feats, cam.width, cam.height, K, tiles=done)
+    t_render = time.perf_counter() - t0
+    frame_1 = t_proj + t_bin + t_render * n_tiles / len(done)
     if limiter is not None:
         limiter.unregister()
-    return dict(value=1.0 / frame_s, unit="frames/s", cores=1, kind="oracle",
-                sample="room pose 100: FP64 projection and binning of all 200k Gaussians, "
-                       "Algorithm 1 on %d of %d tiles (%.1f s), extrapolated to the frame"
-                       % (len(done), n_tiles, t_proj + t_bin + t_render))
+
+    # the same sample over a pool of forked workers, one BLAS thread each
+    cores = _host_cores()
+    frame_all, t_pool = None, None
+    if cores > 1:
+        _CPU_SHARED.update(pr=pr, gids=gids, offs=offs, feats=feats, W=cam.width, H=cam.height, K=K)
+        chunks = [done[i::cores] for i in range(cores) if done[i::cores]]
+        ctx = mp.get_context("fork")
+        with ctx.Pool(len(chunks)) as pool:
+            t0 = time.perf_counter()
+            pool.map(_cpu_worker, chunks, chunksize=1)
+            t_pool = time.perf_counter() - t0
+        _CPU_SHARED.clear()
+        frame_all = t_proj + t_bin + t_pool * n_tiles / len(done)
+
+    errors = None
+    if gpu_q is not None:
+        errors = {"reference": "end-to-end FP64 oracle (projection, binning, render) on the "
+                               "sampled tiles of %s" % label,
+                  "quantile": _tile_err(gpu_q, ref_q, done, cam.width, cam.height)}
+        if gpu_d is not None:
+            lens = np.diff(offs)
+            d_tiles = sorted(set(done[:3]) | {int(np.argmax(lens))})
+            ref_d = oracle.render_dense(pr, gids, offs, feats, cam.width, cam.height, tiles=d_tiles)
+            errors["dense"] = _tile_err(gpu_d, ref_d, d_tiles, cam.width, cam.height)
+    one = {"value": round(1.0 / frame_1, 4), "cores": 1}
+    rec = dict(value=round(1.0 / (frame_all or frame_1), 4), unit="frames/s",
+               cores=cores if frame_all else 1, kind="oracle",
+               sample="%s: FP64 projection and binning of all %d Gaussians (%.1f s, one core), "
+                      "Algorithm 1 on %d of %d tiles (%.1f s on one core%s), extrapolated to the "
+                      "frame" % (label, sc.n, t_proj + t_bin, len(done), n_tiles, t_render,
+                                 ", %.1f s on %d processes" % (t_pool, cores) if t_pool else ""),
+               one_core=one)
+    return rec, errors
 
 
 def main():
@@ -312,8 +414,8 @@ def run_room(args):
     torch.cuda.synchronize()
     assert int(states[0].vb.bins.total_pairs.item()) == pairs_total <= capacity
 
-    # per-pose statistics for the algorithmic byte count (untimed)
-    pairs, uniq, nsel = [], [], []
+    # per-pose statistics for the algorithmic byte counts (untimed)
+    pairs, uniq, nsel, pairs_d, uniq_d = [], [], [], [], []
     for v in range(n_views):
         pr, b = states[0].per_view[v]
         offs = b.tile_offsets
@@ -323,6 +425,11 @@ def run_room(args):
         uniq.append(int(torch.unique(g[g >= 0]).numel()))
         nsel.append(float(r["n_sel"].float().mean().item()))
         del r, g
+        d = qr.render_dense(pr, b, s["feats"], W, H)
+        pd, ud = dense_list_prefix(b, d["n_contrib"], W, H)
+        pairs_d.append(pd)
+        uniq_d.append(ud)
+        del d
     tuned, tune_ms = autotune(states[0].bq, wg_per_cu=(0, 3, 8), use_cache=False)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
@@ -333,7 +440,11 @@ def run_room(args):
                                   tuned["wg_per_cu"], overlap=True)
     overlap = dt_ovl < dt_seq
     dt_b, k_b = (dt_ovl, k_ovl) if overlap else (dt_seq, k_seq)
-    dt_d = timed_dense(states[0], args.steps, args.warmup)
+    torch.cuda.synchronize()
+    gpu_q0 = outs[0].cpu().numpy()  # a timed map, checked against the oracle below
+    dt_d, k_d, tuned_d, (dt_d_seq, dt_d_ovl) = timed_dense(states, args.steps, args.warmup)
+    torch.cuda.synchronize()
+    gpu_d0 = outs[0].cpu().numpy()
     frames = args.steps * n_views
     q_fps = frames / dt_b
     d_fps = frames / dt_d
@@ -349,6 +460,14 @@ def run_room(args):
     kernel = ("render_quantile_batched_grid_kernel<0, 0, 0>" if tuned["wg_per_cu"] == 0
               else "render_quantile_batched_kernel<0, 0, 0>")
     traffic = measured_traffic(kernel, "room")
+    # the dense launch: the same output and per-pixel scalars, the records of
+    # each tile's list up to its last blended entry, each blended Gaussian's
+    # row once
+    bytes_d = float(np.sum([n_px * (D * 4 + 8) + p * 28 + (n_tiles + 1) * 8 + u * D * 4
+                            for p, u in zip(pairs_d, uniq_d)]))
+    achieved_d = bytes_d / (k_d * 1e-3) / 1e9
+    kernel_d = ("render_dense_batched_grid_kernel<0>" if tuned_d["wg_per_cu"] == 0
+                else "render_dense_batched_kernel<0>")
 
     # side result: the same steps writing bfloat16 maps (half the output
     # bytes; the map is the float32 result rounded at the store)
@@ -378,9 +497,9 @@ def run_room(args):
     # side results: Stratified-K (Appendix) and the Top-K sampler (the
     # paper's speed comparison, Sec. 4.2) on the same binned poses, the
     # batched launch alone (the front is the same as Q-Render's)
-    def side_render(selection):
+    def side_render(selection, k_side=K):
         from paper_2512_20927_amd.batched import BatchedQuantile
-        bq_s = BatchedQuantile(states[0].bq._views, K, D, L.QR_F32,
+        bq_s = BatchedQuantile(states[0].bq._views, k_side, D, L.QR_F32,
                                qr.RenderParams(selection=selection).c())
         tuned_s, _ = autotune(bq_s, wg_per_cu=(0, 3, 8), use_cache=False)
         for _ in range(args.warmup):
@@ -397,14 +516,17 @@ def run_room(args):
                 "quantile_render_frames_per_s": round(n_views / (k_seq * 1e-3), 2),
                 "batched_launch": {k: tuned_s[k] for k in ("schedule", "wg_per_cu")}}
 
-    strat_side = topk_side = None
+    strat_side = topk_side = k40_side = None
     if not args.renders_only:
         strat_side = side_render(L.QR_SELECT_STRATIFIED)
         topk_side = side_render(L.QR_SELECT_TOPK)
+        # K = 40: the paper's trained setting (its ablation and memory table)
+        k40_side = side_render(L.QR_SELECT_QUANTILE, 40)
+        k40_side["K"] = 40
 
-    cpu = None
+    cpu = errors = None
     if args.cpu_budget > 0 and not args.renders_only:
-        cpu = cpu_reference(sc, cams[0], K, args.cpu_budget)
+        cpu, errors = cpu_reference(sc, cams[0], K, args.cpu_budget, gpu_q=gpu_q0, gpu_d=gpu_d0)
 
     rec = {
         "metric": METRIC,
@@ -430,6 +552,19 @@ def run_room(args):
         },
         "dense_value": round(d_fps, 2),
         "q_over_dense": round(q_fps / d_fps, 3),
+        "dense": {"protocol": "the dense blend over the same (pose, tile) items in one batched "
+                              "launch after the same front, launch shape autotuned, front "
+                              "overlapped when faster: only the blending rule differs",
+                  "sequential_value": round(frames / dt_d_seq, 2),
+                  "overlapped_value": round(frames / dt_d_ovl, 2),
+                  "render_ms": round(k_d, 4),
+                  "batched_launch": {k: tuned_d[k] for k in ("schedule", "wg_per_cu")},
+                  "roofline": {"bound": "hbm", "kernel": kernel_d, "achieved": round(achieved_d, 1),
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(achieved_d / HBM_PEAK_GBS, 4),
+                               "bytes_per_launch": round(bytes_d)},
+                  "list_prefix_pairs_mean": float(np.mean(pairs_d)),
+                  "blended_unique_mean": float(np.mean(uniq_d))},
         "sequential_value": round(frames / dt_seq, 2),
         "overlapped_value": round(frames / dt_ovl, 2),
         "render_ms": {"quantile_batched_launch": round(k_seq, 4),
@@ -442,9 +577,12 @@ def run_room(args):
                      "traffic": traffic,
                      "bytes_per_launch": round(bytes_batch), "frames_per_launch": n_views},
         "cpu_baseline": cpu,
+        "max_rel_err": errors["quantile"]["max"] if errors else None,
+        "error_vs_oracle": errors,
         "bf16_output": bf16_side,
         "stratified_k": strat_side,
         "top_k": topk_side,
+        "k40": k40_side,
         "autotune_ms": {k: round(v, 3) for k, v in tune_ms.items()},
         "setup_s": round(t_setup, 1),
     }
@@ -491,7 +629,7 @@ def run_precision(args):
         per_k[str(K)] = round(frames / dt, 2)
         render_ms[str(K)] = round(kms, 4)
         tuned_k[str(K)] = {k: tuned[k] for k in ("schedule", "wg_per_cu")}
-    dt_d = timed_dense(states[0], args.steps, args.warmup)
+    dt_d, k_d, tuned_d, _ = timed_dense(states, args.steps, args.warmup)
     d_fps = frames / dt_d
     rec = _base_record(args, per_k["8"], "frames/s", "bf16",
                        "precision: 1M Gaussians, 1296x968, fx=fy=1168.4, 512-D bf16 features "
@@ -499,8 +637,10 @@ def run_precision(args):
                        1e3 * frames / per_k["8"] / args.steps)
     rec.update({"q_fps_per_K": per_k, "dense_value": round(d_fps, 2),
                 "q_over_dense": round(per_k["8"] / d_fps, 3),
-                "render_ms": {"quantile_batched_launch_per_K": render_ms},
+                "render_ms": {"quantile_batched_launch_per_K": render_ms,
+                              "dense_batched_launch": round(k_d, 4)},
                 "batched_launch_per_K": tuned_k,
+                "dense_batched_launch": {k: tuned_d[k] for k in ("schedule", "wg_per_cu")},
                 "workload_stats": {"pairs_mean": float(np.mean(pairs))}})
     print(json.dumps(rec))
 
@@ -647,11 +787,11 @@ def run_rgb(args):
     torch.cuda.synchronize()
     frames = args.steps * nv
     # dense reference images and T after the last Gaussian (for the record)
-    states[0].render_dense()
+    states[0].make_bd().render()
     torch.cuda.synchronize()
     ref = [o[..., :3].clamp(0, 1).clone() for o in outs]
     T_final = float(torch.stack([a.clone() for a in aux_f]).mean().item())
-    dt_d = timed_dense(states[0], args.steps, args.warmup)
+    dt_d, k_d, _, _ = timed_dense(states, args.steps, args.warmup)
     per_k, psnr, render_ms = {}, {}, {}
     for K in (4, 8, 16):
         for st in states:
@@ -674,7 +814,8 @@ def run_rgb(args):
     rec.update({"q_fps_per_K": per_k, "dense_value": round(d_fps, 2),
                 "q_over_dense": round(per_k["8"] / d_fps, 3),
                 "psnr_q_vs_dense_db": psnr, "dense_T_final_mean": round(T_final, 5),
-                "render_ms": {"quantile_batched_launch_per_K": render_ms}})
+                "render_ms": {"quantile_batched_launch_per_K": render_ms,
+                              "dense_batched_launch": round(k_d, 4)}})
     print(json.dumps(rec))
 
 def run_batched(args):

@@ -377,6 +377,22 @@ int qr_render_quantile_batched(void* stream, int32_t n_views, const qr_view* vie
                                void* workspace, size_t workspace_bytes);
 
 /*
+ * qr_render_dense_batched - the dense blend of Eq. 1 (as qr_render_dense) for
+ * many views in one launch over the same (view, tile) items, schedules,
+ * launch modes and workspace as qr_render_quantile_batched, so that the two
+ * renderers differ only in which Gaussians of each ray they blend. In each
+ * qr_view record, `T_q` receives T_final and `n_sel` receives n_contrib of
+ * qr_render_dense (both nullable); K does not apply. Each item is rendered
+ * exactly as qr_render_dense renders that tile (bit-identical).
+ * Errors: as qr_render_quantile_batched; QR_ERR_UNSUPPORTED for a bfloat16
+ * output type.
+ */
+int qr_render_dense_batched(void* stream, int32_t n_views, const qr_view* views,
+                            const qr_params* prm, int32_t dtype, int32_t dim,
+                            const uint32_t* schedule, int64_t n_items,
+                            int32_t n_workgroups, void* workspace, size_t workspace_bytes);
+
+/*
  * qr_batch_schedule - builds a schedule for qr_render_quantile_batched on the
  * device, without a host round trip: every (view, tile) item, ordered by the
  * length of its tile list, longest first, in power-of-two length classes
@@ -441,10 +457,10 @@ int qr_render_quantile_backward(void* stream, int32_t width, int32_t height,
  * them). Writes the mean launch time to timings_ms[i * n_wg + j] (host) and
  * the fastest candidate to *best_schedule, *best_wg_per_cu (host). The
  * rendered outputs are those of the last launch. Other arguments as for
- * qr_render_quantile_batched; workspace >= 32 bytes if any w > 0.
+ * qr_render_quantile_batched; workspace >= 32 bytes if any w > 0. K = 0
+ * times qr_render_dense_batched over the same candidates instead.
  * Errors: QR_ERR_INVALID_ARG for null host pointers, counts < 1 or w outside
- * [0, 64]; any error of qr_render_quantile_batched; QR_ERR_HIP for event
- * failures.
+ * [0, 64]; any error of the timed launch; QR_ERR_HIP for event failures.
  */
 int qr_autotune_batched(void* stream, int32_t n_views, const qr_view* views,
                         const qr_params* prm, int32_t K, int32_t dtype, int32_t dim,

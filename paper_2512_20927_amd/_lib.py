@@ -34,6 +34,7 @@ EXPORTED = [
     "qr_render_quantile_batched", "qr_batch_schedule", "qr_project_views", "qr_bin_sort_views",
     "qr_render_quantile_batched_backward", "qr_autotune_batched", "qr_devoxelize",
     "qr_devoxelize_backward", "qr_sh_to_rgb", "qr_sh_to_rgb_views", "qr_bin_sort_noalloc",
+    "qr_render_dense_batched",
 ]
 QR_BATCH_TILE_BITS = 20
 
@@ -95,6 +96,7 @@ def _load():
         "qr_render_quantile_backward": ([P, i32, i32, prm_p, i32, P, P, P, P, P, i32, P, i32, P, P, P, P], i32),
         "qr_quantize_features": ([P, i64, i32, P, i32, P, P], i32),
         "qr_render_quantile_batched": ([P, i32, P, prm_p, i32, i32, i32, P, i64, i32, P, sz], i32),
+        "qr_render_dense_batched": ([P, i32, P, prm_p, i32, i32, P, i64, i32, P, sz], i32),
         "qr_batch_schedule": ([P, i32, P, P, i64, P, P, sz], i32),
         "qr_render_quantile_batched_backward": ([P, i32, P, P, prm_p, i32, i32, i32, P, i64, i32, P, sz], i32),
         "qr_sh_to_rgb": ([P, i64, i32, P, P, i32, cam_p, P, i32], i32),
@@ -425,6 +427,22 @@ def qr_render_quantile_batched(n_views, views_dev, params, K, dtype_code, dim, s
                                            _ptr(schedule), schedule.numel(), n_workgroups,
                                            _ptr(workspace) if workspace is not None else None,
                                            ws_bytes))
+
+
+def qr_render_dense_batched(n_views, views_dev, params, dtype_code, dim, schedule, n_workgroups,
+                            workspace, stream=None):
+    """The dense blend over the same views table and schedule as
+    qr_render_quantile_batched; each view's T_q / n_sel fields receive
+    T_final / n_contrib."""
+    if views_dev.numel() < n_views * ctypes.sizeof(qr_view):
+        raise ValueError("views_dev is smaller than n_views qr_view records")
+    _need(schedule, 0, I32, "schedule")
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(_LIB.qr_render_dense_batched(_stream(stream), n_views, _ptr(views_dev),
+                                        ctypes.byref(params), dtype_code, dim, _ptr(schedule),
+                                        schedule.numel(), n_workgroups,
+                                        _ptr(workspace) if workspace is not None else None,
+                                        ws_bytes))
 
 
 def qr_render_quantile_batched_backward(n_views, views_dev, grads_dev, params, K, dtype_code, dim,

@@ -12,6 +12,8 @@ and ``heavy`` (longest tile lists first, built on the device by
 autotuner times the candidates (schedule x workgroups per CU) with HIP events
 and caches the winner as JSON keyed by device, shapes and K. ``backward``
 runs the Q-Render backward of every view in one launch over the same items.
+``BatchedDense`` renders the dense blend over the same items and launch
+shapes.
 """
 
 from __future__ import annotations
@@ -42,7 +44,7 @@ def _check_tensor(t, numel, dtypes, name, device):
         raise ValueError("%s is on %s, the batch on %s" % (name, t.device, device))
 
 
-def validate_views(views, K: int, dim: int, dtype_code: int, params):
+def validate_views(views, K: int, dim: int, dtype_code: int, params, dense: bool = False):
     """Host-side checks of every view record before its pointers are packed
     into the device table: the batched kernels read sizes from the records
     and cannot check the buffers behind them, so a mismatch here would be an
@@ -50,7 +52,7 @@ def validate_views(views, K: int, dim: int, dtype_code: int, params):
     and field."""
     if not views:
         raise ValueError("a batch needs at least one view")
-    if not 1 <= K <= L.QR_MAX_K:
+    if not dense and not 1 <= K <= L.QR_MAX_K:
         raise ValueError("K = %d outside [1, %d]" % (K, L.QR_MAX_K))
     out_dt = (torch.bfloat16,) if params.out_dtype == L.QR_BF16 else L.F32
     feat_dt = tuple(t for t, c in L.DTYPE_CODE.items() if c == dtype_code)
@@ -80,12 +82,12 @@ def validate_views(views, K: int, dim: int, dtype_code: int, params):
 
 
 class BatchedQuantile:
-    def __init__(self, views, K: int, dim: int, dtype_code: int, params):
+    def __init__(self, views, K: int, dim: int, dtype_code: int, params, _dense: bool = False):
         """views: list of dicts with tile_offsets, sorted_gid, means2d,
         conic_opacity, features, feature_scale (or None), out, T_q, n_sel (or
         None), width, height (all tensors on one device); checked by
         validate_views before anything is packed."""
-        validate_views(views, K, dim, dtype_code, params)
+        validate_views(views, K, dim, dtype_code, params, dense=_dense)
         self.n_views = len(views)
         self.K, self.dim, self.dtype_code, self.params = K, dim, dtype_code, params
         dev = views[0]["out"].device
@@ -159,6 +161,35 @@ class BatchedQuantile:
         shapes = sorted({(v["width"], v["height"]) for v in self._views})
         return "%s|views=%d|%s|D=%d|K=%d|dtype=%d" % (self.device_name, self.n_views, shapes,
                                                       self.dim, self.K, self.dtype_code)
+
+
+class BatchedDense(BatchedQuantile):
+    """The dense blend (Eq. 1) over the same view table, items, schedules and
+    launch shapes as BatchedQuantile: the two renderers then differ only in
+    which Gaussians of each ray they blend. Each view's ``T_q`` / ``n_sel``
+    tensors receive T_final / n_contrib. ``autotune`` works on it unchanged
+    (K = 0 selects the dense launch in the library's autotuner)."""
+
+    def __init__(self, views, dim: int, dtype_code: int, params):
+        if params.out_dtype != L.QR_F32:
+            raise ValueError("the dense blend writes float32 maps only")
+        # K = 0 marks the dense launch (the library's autotuner times it)
+        super().__init__(views, 0, dim, dtype_code, params, _dense=True)
+
+    def render(self, kind: str = "natural", wg_per_cu: int = 0, start_event=None):
+        sched = self.schedule(kind)
+        if start_event is not None:
+            start_event.record()
+        L.qr_render_dense_batched(self.n_views, self.views_dev, self.params, self.dtype_code,
+                                  self.dim, sched, self.n_cu * wg_per_cu,
+                                  self.counter if wg_per_cu > 0 else None)
+
+    def set_grads(self, grads):
+        raise NotImplementedError("the batched launch has no dense backward; use "
+                                  "qr_render_dense_backward per view")
+
+    def backward(self, kind: str = "natural", wg_per_cu: int = 0):
+        raise NotImplementedError("the batched launch has no dense backward")
 
 
 def default_cache_path() -> str:

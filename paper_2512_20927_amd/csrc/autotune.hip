@@ -1,6 +1,7 @@
-// Launch-shape autotuner of the batched Q-Render (host code): times every
-// (schedule, workgroups per CU) candidate of qr_render_quantile_batched with
-// HIP events on the caller's stream and reports the fastest.
+// Launch-shape autotuner of the batched renderers (host code): times every
+// (schedule, workgroups per CU) candidate of qr_render_quantile_batched (or,
+// with K = 0, of qr_render_dense_batched) with HIP events on the caller's
+// stream and reports the fastest.
 #include <vector>
 
 #include "common.h"
@@ -41,6 +42,9 @@ extern "C" int qr_autotune_batched(void* stream, int32_t n_views, const qr_view*
     for (int j = 0; j < n_wg && rc == QR_OK; ++j) {
       const int nwg = wg_per_cu[j] * n_cu;
       auto launch = [&]() {
+        if (K == 0)
+          return qr_render_dense_batched(stream, n_views, views, prm, dtype, dim, schedules[i],
+                                         n_items, nwg, workspace, workspace_bytes);
         return qr_render_quantile_batched(stream, n_views, views, prm, K, dtype, dim, schedules[i],
                                           n_items, nwg, workspace, workspace_bytes);
       };

@@ -1,196 +1,388 @@
 // Dense alpha-blend forward (Eq. 1: out = sum_i T_i alpha'_i f_i over every
 // Gaussian on the ray, stopping before T drops below T_eps).
 //
-// Per tile the output is a contraction W [256 px x G] . F [G x D] where
+// Per tile the output is a contraction W [px x G] . F [G x D] where
 // W[p, g] = T_{p,g} alpha'_{p,g} (zero off the ray or after the stop) and F
-// holds the feature rows of the tile's depth-sorted list. One workgroup
-// computes one tile x one 128-column slice of D:
-//   - 32 list entries at a time, each pixel thread walks its transmittance
-//     chain and writes its 32 weights into LDS; the 32 feature rows (slice)
-//     are decoded to float32 alongside;
-//   - both operands are split into bfloat16 pairs x = x_hi + x_lo (x_hi the
-//     rounded value, x_lo the rounded remainder) and the product is formed as
-//     W_hi F_hi + W_hi F_lo + W_lo F_hi on v_mfma_f32_16x16x32_bf16 with
-//     float32 accumulation (bf16 features are exact in x_hi, so their F_lo
-//     term is dropped). The omitted W_lo F_lo term and the second roundings
-//     are below 2^-16 of each product, i.e. float32-class accuracy at the
-//     bf16 matrix rate;
-//   - each wave64 owns 64 pixels (4 pixel rows) x 128 columns: 32
-//     accumulator tiles of 16x16;
-//   - the workgroup leaves the list once every pixel has stopped.
-// The weight walk is recomputed by each of the D/128 slices of a tile.
+// holds the feature rows of the tile's depth-sorted list. The unit of work is
+// a strip of 64 pixels (4 rows of a 16x16 tile) over all D columns, so every
+// pixel's transmittance chain is walked once:
+//   - each lane of each wave owns one pixel of the strip (the same pixel in
+//     all four waves); the list is taken 32 entries at a time and wave q
+//     evaluates alpha' of entries 8q .. 8q+7 for its lane's pixel. The four
+//     partial products of (1 - alpha') are exchanged through LDS, so each wave
+//     knows T at the start of its eight entries and forms their weights; the
+//     stop test is applied in list order within the eight, and a stop in an
+//     earlier eight leaves T below T_eps there, which stops the later ones at
+//     their first entry too (their T differs from the sequential chain's only
+//     in rounding, and one more factor (1 - alpha') <= 1 - alpha_min takes it
+//     below T_eps). Every wave then folds the four results into the pixel's
+//     T, stop flag and last blended position identically;
+//   - the weights go to LDS as bfloat16 pairs w = w_hi + w_lo; each wave
+//     contracts them with its own column groups of F on
+//     v_mfma_f32_16x16x32_bf16 as out^T = F^T W^T, both operands split into
+//     bfloat16 pairs and the product formed as F_hi W_hi + F_lo W_hi +
+//     F_hi W_lo with float32 accumulation (bfloat16 features are exact in
+//     F_hi, so their F_lo term is dropped): float32-class accuracy (below
+//     2^-16 of each product) at the bfloat16 matrix rate;
+//   - the MFMA rows of a 64-column group are permuted (row i of column tile c
+//     is column 16 (i % 4) + 4 (i / 4) + c), so that a lane's operand values
+//     for the group's four column tiles are four consecutive features of one
+//     row (one 16-byte load per list entry) and its results for one pixel are
+//     four consecutive features (one 16-byte store);
+//   - feature rows of a batch are requested before the walk, so their loads
+//     overlap it; 16-pixel rows of the strip that take nothing from a batch
+//     skip their MFMAs; the strip leaves the list once all 64 pixels stopped.
+// Widths above 512 are rendered in passes of 512 columns, each walking again.
 #include "common.h"
+#include "quantile_select.h"
 #include "render_common.h"
 
 namespace qr {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kDC = 128;            // feature columns per workgroup
-constexpr int kGB = 32;             // list entries per batch (= MFMA K)
-constexpr int kKS = kGB + 8;        // LDS stride (bf16) of a 32-entry row: 80 B
+constexpr int kStripRows = 4;                      // tile rows per strip
+constexpr int kStripPix = kTile * kStripRows;      // 64: one pixel per lane
+constexpr int kStrips = kTile / kStripRows;        // 4 strips per tile
+constexpr int kDB = 32;                            // list entries per batch (MFMA K)
+constexpr int kDQ = kDB / 4;                       // entries each wave walks per batch
+constexpr int kGrpCols = 64;                       // columns of a group (4 MFMA column tiles)
+constexpr int kWaveGroups = 2;                     // groups per wave and pass
+constexpr int kPassCols = 4 * kWaveGroups * kGrpCols;  // 512 columns per pass
+constexpr int kWS = kDB + 8;                       // LDS row stride (bf16) of a pixel's weights
+constexpr uint32_t kStopBit = 0x100u;
 
-__device__ __forceinline__ void split_bf16(float x, __bf16* hi, __bf16* lo) {
-  const __bf16 h = static_cast<__bf16>(x);
-  *hi = h;
-  *lo = static_cast<__bf16>(x - static_cast<float>(h));
+struct DenseLds {
+  __attribute__((aligned(16))) __bf16 whi[kStripPix * kWS];
+  __attribute__((aligned(16))) __bf16 wlo[kStripPix * kWS];
+  float2 mean[kDB];
+  float4 co[kDB];
+  // ids of the batch, double-buffered by batch parity: the second column
+  // group's loads read them after the last barrier of the batch, while wave
+  // 0 may already be staging the next batch
+  int gid[2][kDB];
+  float part[4][kStripPix];   // product of (1 - alpha') over a wave's eight entries
+  float tend[4][kStripPix];   // T after a wave's eight entries (before its stop)
+  uint32_t info[4][kStripPix];  // last blended entry (0..7, 0xFF none) | kStopBit
+  unsigned long long busy[4];   // pixels with a non-zero weight, per wave
+};
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = static_cast<__bf16>(x);
+  lo = static_cast<__bf16>(x - static_cast<float>(hi));
+}
+
+// Four consecutive features (d .. d+3) of row g as raw loads: float32 values,
+// or bfloat16 codes in the low 8 bytes.
+template <int DT>
+__device__ __forceinline__ f32x4 load_raw4(const GView& v, int g, int dim, int d) {
+  if constexpr (DT == QR_BF16) {
+    const u32x2 r = *reinterpret_cast<const QR_GLOBAL u32x2*>(
+        static_cast<const QR_GLOBAL uint16_t*>(v.feats) + static_cast<int64_t>(g) * dim + d);
+    return f32x4{__uint_as_float(r.x), __uint_as_float(r.y), 0.f, 0.f};
+  } else {
+    const float4 x = load_feat4_global<DT>(v.feats, v.scale, g, dim, d);
+    return f32x4{x.x, x.y, x.z, x.w};
+  }
+}
+
+// One 64-pixel strip of one tile: Eq. 1 for its pixels, all `dim` columns.
+// Called by all 256 threads; every barrier is reached by every wave the same
+// number of times (loop bounds and exits are uniform over the workgroup).
+template <int DT>
+__device__ void dense_strip(const GView& v, int tile, int strip, int dim, const qr_params& prm,
+                            DenseLds& L) {
+  constexpr bool kSplitF = DT != QR_BF16;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int kb = lane >> 4;  // MFMA k-block of the lane: entries 8 kb .. 8 kb + 7
+  const int ci = lane & 15;  // MFMA row / column index of the lane
+  const int W = v.W, H = v.H;
+  const int tiles_x = (W + kTile - 1) / kTile;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  // the lane's pixel in the walk (the same in every wave)
+  const int px = tx * kTile + ci;
+  const int py = ty * kTile + strip * kStripRows + kb;
+  const bool inside = px < W && py < H;
+  const float pxc = px + 0.5f, pyc = py + 0.5f;
+  const int lo = static_cast<int>(v.tile_offsets[tile]);
+  const int hi = static_cast<int>(v.tile_offsets[tile + 1]);
+  const int coff = 16 * (ci & 3) + 4 * (ci >> 2);  // the lane's columns in a group
+  int par = 0;  // parity of the batches staged so far (selects the id buffer)
+
+  for (int c0 = 0; c0 < dim; c0 += kPassCols) {
+    // this wave's column groups in the pass: base column and width (0: none)
+    int gbase[kWaveGroups], gw[kWaveGroups];
+#pragma unroll
+    for (int k = 0; k < kWaveGroups; ++k) {
+      gbase[k] = c0 + (wave + 4 * k) * kGrpCols;
+      gw[k] = max(0, min(kGrpCols, dim - gbase[k]));
+    }
+    float T = 1.f;
+    bool done = !inside;
+    int ncon = 0;
+    f32x4 acc[kWaveGroups][4][4];
+#pragma unroll
+    for (int k = 0; k < kWaveGroups; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) acc[k][c][p] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int batch = lo; batch < hi; batch += kDB) {
+      // the pixel states are identical in every wave: a uniform exit
+      if (__ballot(!done) == 0ull) break;
+      const int cnt = min(kDB, hi - batch);
+      // records of the batch (the previous batch's were last read before the
+      // second barrier of its iteration, which every wave has passed; its ids
+      // are in the other buffer)
+      int* const gid = L.gid[par];
+      par ^= 1;
+      if (tid < cnt) {
+        const int g = static_cast<int>(v.sorted_gid[batch + tid]);
+        gid[tid] = g;
+        const f32x2 m = v.means2d[g];
+        const f32x4 c = v.conic_opacity[g];
+        L.mean[tid] = make_float2(m.x, m.y);
+        L.co[tid] = make_float4(c.x, c.y, c.z, c.w);
+      }
+      __syncthreads();
+
+      // feature rows of the batch for this wave's first group, requested now
+      // so that the loads overlap the walk (the second group's are requested
+      // before the first group's MFMAs)
+      f32x4 raw[8];
+      const auto load_group = [&](int k) {
+        const bool use = coff < gw[k];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int e = 8 * kb + t;
+          raw[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+          if (use && e < cnt) raw[t] = load_raw4<DT>(v, gid[e], dim, gbase[k] + coff);
+        }
+      };
+      load_group(0);
+
+      // walk, first half: alpha' of this wave's eight entries and the product
+      // of their (1 - alpha')
+      float al[kDQ];
+      float part = 1.f;
+#pragma unroll
+      for (int j = 0; j < kDQ; ++j) {
+        const int e = kDQ * wave + j;
+        al[j] = 0.f;
+        if (e < cnt && !done) {
+          const float a = gauss_alpha(L.mean[e], L.co[e], pxc, pyc, prm.alpha_max);
+          if (a >= prm.alpha_min) {
+            al[j] = a;
+            part *= 1.f - a;
+          }
+        }
+      }
+      L.part[wave][lane] = part;
+      __syncthreads();
+
+      // second half: T at the start of the eight entries, their weights in
+      // list order with the stop test
+      float Tl = T;
+      for (int q = 0; q < wave; ++q) Tl *= L.part[q][lane];
+      bool stopped = false;
+      uint32_t last = 0xFFu;
+      bool any = false;
+      typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+      bf16x8v whi, wlo;
+#pragma unroll
+      for (int j = 0; j < kDQ; ++j) {
+        float w = 0.f;
+        if (al[j] > 0.f && !stopped) {
+          const float T_test = Tl * (1.f - al[j]);
+          if (T_test < prm.T_eps) {
+            stopped = true;
+          } else {
+            w = al[j] * Tl;
+            Tl = T_test;
+            last = static_cast<uint32_t>(j);
+          }
+        }
+        any |= w != 0.f;
+        __bf16 h, l;
+        split_bf16(w, h, l);
+        whi[j] = h;
+        wlo[j] = l;
+      }
+      *reinterpret_cast<bf16x8v*>(&L.whi[lane * kWS + kDQ * wave]) = whi;
+      *reinterpret_cast<bf16x8v*>(&L.wlo[lane * kWS + kDQ * wave]) = wlo;
+      L.tend[wave][lane] = Tl;
+      L.info[wave][lane] = last | (stopped ? kStopBit : 0u);
+      const unsigned long long b = __ballot(any);
+      if (lane == 0) L.busy[wave] = b;
+      __syncthreads();
+
+      // the pixel's state after the batch, folded in list order (the same in
+      // every wave)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!done) {
+          const uint32_t inf = L.info[q][lane];
+          // T moves only with a blended entry (T_test >= T_eps), so it never
+          // falls below T_eps
+          if ((inf & 0xFFu) != 0xFFu) {
+            ncon = batch - lo + kDQ * q + static_cast<int>(inf & 0xFFu) + 1;
+            T = L.tend[q][lane];
+          }
+          if (inf & kStopBit) done = true;
+        }
+      }
+      const unsigned long long busy = L.busy[0] | L.busy[1] | L.busy[2] | L.busy[3];
+
+      // F^T W^T on the matrix cores, one column group at a time: A = this
+      // wave's features (rows permuted within the group), B = the weights of
+      // 16 pixels
+#pragma unroll
+      for (int k = 0; k < kWaveGroups; ++k) {
+        if (gw[k] == 0) continue;
+        bf16x8 ahi[4], alo[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            if constexpr (kSplitF) {
+              __bf16 h, l;
+              split_bf16(raw[t][c], h, l);
+              ahi[c][t] = h;
+              alo[c][t] = l;
+            } else {
+              // bfloat16 codes: two per 32-bit word, column c in word c / 2
+              const uint32_t word = __float_as_uint(raw[t][c >> 1]);
+              const uint16_t code = static_cast<uint16_t>((c & 1) ? (word >> 16) : (word & 0xFFFFu));
+              ahi[c][t] = __builtin_bit_cast(__bf16, code);
+            }
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          if (((busy >> (16 * p)) & 0xFFFFull) == 0ull) continue;
+          const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(&L.whi[(16 * p + ci) * kWS + 8 * kb]);
+          const bf16x8 blo = *reinterpret_cast<const bf16x8*>(&L.wlo[(16 * p + ci) * kWS + 8 * kb]);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            acc[k][c][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[c], bhi, acc[k][c][p], 0, 0, 0);
+            acc[k][c][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[c], blo, acc[k][c][p], 0, 0, 0);
+            if constexpr (kSplitF)
+              acc[k][c][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[c], bhi, acc[k][c][p], 0, 0, 0);
+          }
+        }
+        if (k + 1 < kWaveGroups) load_group(k + 1);
+      }
+    }
+
+    // results: lane (kb, ci) holds, for pixel row p of the strip and column
+    // tile c, out^T rows 4 kb + r (r = 0..3), i.e. columns 16 r + 4 kb + c of
+    // pixel ci: four consecutive columns per (r, p)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int ox = tx * kTile + ci, oy = ty * kTile + strip * kStripRows + p;
+      if (ox >= W || oy >= H) continue;
+      QR_GLOBAL float* dst = v.out + (static_cast<int64_t>(oy) * W + ox) * dim;
+#pragma unroll
+      for (int k = 0; k < kWaveGroups; ++k) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = 16 * r + 4 * kb;
+          if (col < gw[k])
+            store_stream(reinterpret_cast<QR_GLOBAL float4*>(dst + gbase[k] + col),
+                         make_float4(acc[k][0][p][r], acc[k][1][p][r], acc[k][2][p][r], acc[k][3][p][r]));
+        }
+      }
+    }
+    if (c0 == 0 && wave == 0 && inside) {
+      const int pix = py * W + px;
+      if (v.T_q) v.T_q[pix] = T;
+      if (v.n_sel) v.n_sel[pix] = ncon;
+    }
+  }
+}
+
+// One view: one workgroup per (tile, strip); the four strips of a tile are
+// consecutive units and every XCD receives a contiguous run of units.
+template <int DT>
+__global__ void __launch_bounds__(kTilePix, 2)
+render_dense_kernel(ViewArgs v, int n_units, int dim, qr_params prm) {
+  __shared__ DenseLds L;
+  const int u = xcd_remap(blockIdx.x, n_units);
+  dense_strip<DT>(to_global(v), u / kStrips, u % kStrips, dim, prm, L);
+}
+
+// Many views, one workgroup per (item, strip) unit of the schedule.
+template <int DT>
+__global__ void __launch_bounds__(kTilePix, 2)
+render_dense_batched_grid_kernel(const qr_view* __restrict__ views,
+                                 const uint32_t* __restrict__ schedule, int n_units, int dim,
+                                 qr_params prm) {
+  __shared__ DenseLds L;
+  const int u = xcd_remap(blockIdx.x, n_units);
+  const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[u / kStrips]);
+  const GView v = to_global(view_args(views[packed >> kViewShift]));
+  dense_strip<DT>(v, static_cast<int>(packed & kTileMask), u % kStrips, dim, prm, L);
+}
+
+// Many views, persistent workgroups over (item, strip) units through one
+// work counter per XCD (the same queue discipline as the batched Q-Render
+// launch: a workgroup takes units of its XCD's contiguous range of the
+// schedule, then of the others').
+constexpr int kDenseQueues = 8;
+
+__device__ __forceinline__ uint32_t dense_queue_begin(int64_t n_units, int q) {
+  return static_cast<uint32_t>(n_units * q / kDenseQueues);
 }
 
 template <int DT>
 __global__ void __launch_bounds__(kTilePix, 2)
-render_dense_kernel(int W, int H, int tiles_x, int n_tiles, qr_params prm,
-                    const uint32_t* __restrict__ tile_offsets, const uint32_t* __restrict__ sorted_gid,
-                    const float2* __restrict__ means2d, const float4* __restrict__ conic_opacity,
-                    const void* __restrict__ feats, const float* __restrict__ scale, int dim,
-                    float* __restrict__ out, float* __restrict__ T_final,
-                    int32_t* __restrict__ n_contrib) {
-  constexpr bool kSplitF = DT != QR_BF16;
-  // A operand rows: one per pixel, 32 entries; B operand rows: one per column
-  __shared__ __attribute__((aligned(16))) __bf16 s_Ahi[kTilePix * kKS];
-  __shared__ __attribute__((aligned(16))) __bf16 s_Alo[kTilePix * kKS];
-  __shared__ __attribute__((aligned(16))) __bf16 s_Bhi[kDC * kKS];
-  __shared__ __attribute__((aligned(16))) __bf16 s_Blo[kSplitF ? kDC * kKS : 8];
-  __shared__ float2 s_mean[kGB];
-  __shared__ float4 s_co[kGB];
-  __shared__ int s_gid[kGB];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int tile = xcd_remap(blockIdx.x, n_tiles);
-  const int d0 = blockIdx.y * kDC;
-  const int dc = min(kDC, dim - d0);  // multiple of 16
-  const int n_nt = dc >> 4;
-  const int dc4 = dc >> 2;
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int px = tx * kTile + (tid % kTile);
-  const int py = ty * kTile + (tid / kTile);
-  const bool inside = px < W && py < H;
-  const float pxc = px + 0.5f, pyc = py + 0.5f;
-  const int lo = static_cast<int>(tile_offsets[tile]);
-  const int hi = static_cast<int>(tile_offsets[tile + 1]);
-
-  float T = 1.f;
-  int ncon = 0;
-  bool done = !inside;
-  floatx4 acc[4][8];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-  for (int batch = lo; batch < hi; batch += kGB) {
-    if (__syncthreads_count(!done) == 0) break;
-    const int cnt = min(kGB, hi - batch);
-    if (tid < cnt) {
-      const int g = static_cast<int>(sorted_gid[batch + tid]);
-      s_gid[tid] = g;
-      s_mean[tid] = means2d[g];
-      s_co[tid] = conic_opacity[g];
+render_dense_batched_kernel(const qr_view* __restrict__ views, const uint32_t* __restrict__ schedule,
+                            int64_t n_units, uint32_t* __restrict__ counter, int dim, qr_params prm) {
+  __shared__ DenseLds L;
+  __shared__ uint32_t s_unit[2];
+  const int home = static_cast<int>(blockIdx.x % kDenseQueues);
+  for (int it = 0;; it ^= 1) {
+    if (threadIdx.x == 0) {
+      uint32_t unit = 0xFFFFFFFFu;
+      for (int d = 0; d < kDenseQueues; ++d) {
+        const int q = (home + d) % kDenseQueues;
+        const uint32_t b = dense_queue_begin(n_units, q), e = dense_queue_begin(n_units, q + 1);
+        if (b == e) continue;
+        const uint32_t i = atomicAdd(&counter[q], 1u);
+        if (i < e - b) {
+          unit = b + i;
+          break;
+        }
+      }
+      s_unit[it] = unit;
     }
     __syncthreads();
-    // feature slice of the batch, split to bf16, stored column-major (B
-    // operand: 8 consecutive entries of one column per lane); missing rows
-    // are zero
-    for (int e = tid; e < kGB * dc4; e += kTilePix) {
-      const int r = e / dc4, c4 = e - r * dc4;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (r < cnt) v = load_feat4<DT>(feats, scale, s_gid[r], dim, d0 + 4 * c4);
-      const float vv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int col = 4 * c4 + i;
-        if constexpr (kSplitF) {
-          split_bf16(vv[i], &s_Bhi[col * kKS + r], &s_Blo[col * kKS + r]);
-        } else {
-          s_Bhi[col * kKS + r] = static_cast<__bf16>(vv[i]);  // exact: the value is bf16
-        }
-      }
-    }
-    // per-pixel weights of the batch (Eq. 1), in list order
-    __bf16* arow_hi = s_Ahi + tid * kKS;
-    __bf16* arow_lo = s_Alo + tid * kKS;
-    bool any_w = false;
-    for (int j = 0; j < kGB; ++j) {
-      float w = 0.f;
-      if (j < cnt && !done) {
-        const float alpha = gauss_alpha(s_mean[j], s_co[j], pxc, pyc, prm.alpha_max);
-        if (alpha >= prm.alpha_min) {
-          const float T_test = T * (1.f - alpha);
-          if (T_test < prm.T_eps) {
-            done = true;
-          } else {
-            w = alpha * T;
-            T = T_test;
-            ncon = batch - lo + j + 1;
-          }
-        }
-      }
-      any_w |= w != 0.f;
-      split_bf16(w, &arow_hi[j], &arow_lo[j]);
-    }
-    // a wave whose 64 pixels take nothing from this batch skips its MFMAs
-    // (thread tid is pixel tid, so wave w's pixels are exactly its A rows)
-    const bool wave_busy = __ballot(any_w) != 0ull;
-    __syncthreads();
-    if (!wave_busy) continue;
-    // W[64 px x 32] . F[32 x dc] for this wave's 64 pixels
-    const int kq = (lane >> 4) * 8;  // this lane's 8 consecutive entries
-    const int row = lane & 15;
-    bf16x8 ahi[4], alo[4];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      const int p = wave * 64 + mt * 16 + row;
-      ahi[mt] = *reinterpret_cast<const bf16x8*>(&s_Ahi[p * kKS + kq]);
-      alo[mt] = *reinterpret_cast<const bf16x8*>(&s_Alo[p * kKS + kq]);
-    }
-#pragma unroll
-    for (int nt = 0; nt < 8; ++nt) {
-      if (nt < n_nt) {
-        const int col = nt * 16 + row;
-        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(&s_Bhi[col * kKS + kq]);
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt], bhi, acc[mt][nt], 0, 0, 0);
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[mt], bhi, acc[mt][nt], 0, 0, 0);
-        }
-        if constexpr (kSplitF) {
-          const bf16x8 blo = *reinterpret_cast<const bf16x8*>(&s_Blo[col * kKS + kq]);
-#pragma unroll
-          for (int mt = 0; mt < 4; ++mt)
-            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[mt], blo, acc[mt][nt], 0, 0, 0);
-        }
-      }
-    }
+    const uint32_t unit = __builtin_amdgcn_readfirstlane(s_unit[it]);
+    if (unit >= n_units) break;
+    const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[unit / kStrips]);
+    const GView v = to_global(view_args(views[packed >> kViewShift]));
+    dense_strip<DT>(v, static_cast<int>(packed & kTileMask), static_cast<int>(unit % kStrips), dim,
+                    prm, L);
   }
+}
 
-  if (blockIdx.y == 0 && inside) {
-    const int pix = py * W + px;
-    if (T_final) T_final[pix] = T;
-    if (n_contrib) n_contrib[pix] = ncon;
-  }
-  // accumulator layout: lane holds D[4*(lane/16) + v][lane % 16]
-  const int prow_base = lane >> 4;
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    const int gy = ty * kTile + wave * 4 + mt;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int gx = tx * kTile + 4 * prow_base + v;
-      if (gx < W && gy < H) {
-        float* dst = out + (static_cast<int64_t>(gy) * W + gx) * dim + d0 + (lane & 15);
-#pragma unroll
-        for (int nt = 0; nt < 8; ++nt)
-          if (nt < n_nt) __builtin_nontemporal_store(acc[mt][nt][v], dst + nt * 16);
-      }
-    }
-  }
+__global__ void reset_dense_counter_kernel(uint32_t* __restrict__ c) {
+  if (threadIdx.x < kDenseQueues) c[threadIdx.x] = 0u;
 }
 
 }  // namespace qr
 
 using namespace qr;
+
+#define QR_DENSE_DISPATCH(dt)                         \
+  switch (dt) {                                       \
+    case QR_F32: QR_LAUNCH(QR_F32); break;            \
+    case QR_BF16: QR_LAUNCH(QR_BF16); break;          \
+    default: QR_LAUNCH(QR_FP8_E4M3); break;           \
+  }
 
 extern "C" int qr_render_dense(void* stream, int32_t width, int32_t height, const qr_params* prm,
                                const uint32_t* tile_offsets, const uint32_t* sorted_gid,
@@ -202,22 +394,61 @@ extern "C" int qr_render_dense(void* stream, int32_t width, int32_t height, cons
   if (rc != QR_OK) return rc;
   if (prm->out_dtype != QR_F32)
     return fail(QR_ERR_UNSUPPORTED, "qr_render_dense: float32 output only");
-  const int tiles_x = static_cast<int>(ceil_div(width, kTile));
-  const int tiles_y = static_cast<int>(ceil_div(height, kTile));
-  const int n_tiles = tiles_x * tiles_y;
-  const dim3 grid(n_tiles, static_cast<unsigned>(ceil_div(dim, kDC)));
+  const int64_t n_tiles = ceil_div(width, kTile) * ceil_div(height, kTile);
+  if (n_tiles * kStrips >= (1ll << 31)) return fail(QR_ERR_UNSUPPORTED, "qr_render_dense: image too large");
+  const int n_units = static_cast<int>(n_tiles * kStrips);
   hipStream_t s = as_stream(stream);
-#define QR_LAUNCH(DT)                                                                              \
-  hipLaunchKernelGGL(render_dense_kernel<DT>, grid, dim3(kTilePix), 0, s, width, height, tiles_x,  \
-                     n_tiles, *prm, tile_offsets, sorted_gid,                                      \
-                     reinterpret_cast<const float2*>(means2d),                                     \
-                     reinterpret_cast<const float4*>(conic_opacity), features, feature_scale, dim,  \
-                     out, T_final, n_contrib)
-  switch (dtype) {
-    case QR_F32: QR_LAUNCH(QR_F32); break;
-    case QR_BF16: QR_LAUNCH(QR_BF16); break;
-    default: QR_LAUNCH(QR_FP8_E4M3); break;
-  }
+  const ViewArgs v{width, height, tile_offsets, sorted_gid, reinterpret_cast<const float2*>(means2d),
+                   reinterpret_cast<const float4*>(conic_opacity), features, feature_scale, out,
+                   T_final, n_contrib};
+#define QR_LAUNCH(DT) \
+  hipLaunchKernelGGL(render_dense_kernel<DT>, dim3(n_units), dim3(kTilePix), 0, s, v, n_units, dim, *prm)
+  QR_DENSE_DISPATCH(dtype);
 #undef QR_LAUNCH
   return check_launch("qr_render_dense");
+}
+
+extern "C" int qr_render_dense_batched(void* stream, int32_t n_views, const qr_view* views,
+                                       const qr_params* prm, int32_t dtype, int32_t dim,
+                                       const uint32_t* schedule, int64_t n_items,
+                                       int32_t n_workgroups, void* workspace,
+                                       size_t workspace_bytes) {
+  const char* name = "qr_render_dense_batched";
+  if (n_views <= 0 || n_views > (1 << (32 - kViewShift)))
+    return fail(QR_ERR_INVALID_ARG, "%s: n_views = %d out of range", name, n_views);
+  if (!views || !schedule || !prm) return fail(QR_ERR_INVALID_ARG, "%s: null pointer", name);
+  if (n_workgroups < 0) return fail(QR_ERR_INVALID_ARG, "%s: n_workgroups < 0", name);
+  if (n_workgroups > 0 && (!workspace || workspace_bytes < kDenseQueues * sizeof(uint32_t)))
+    return fail(QR_ERR_CAPACITY, "%s: persistent mode needs a %d-byte workspace", name,
+                static_cast<int>(kDenseQueues * sizeof(uint32_t)));
+  if (n_items < 0 || n_items * kStrips >= (1ll << 31))
+    return fail(QR_ERR_INVALID_ARG, "%s: bad item count", name);
+  if (dtype != QR_F32 && dtype != QR_BF16 && dtype != QR_FP8_E4M3)
+    return fail(QR_ERR_UNSUPPORTED, "%s: unknown dtype %d", name, dtype);
+  if (dim <= 0 || dim % 16 != 0 || dim > QR_MAX_DIM)
+    return fail(QR_ERR_UNSUPPORTED, "%s: dim = %d", name, dim);
+  if (!(prm->alpha_min > 0.f) || !(prm->alpha_max >= prm->alpha_min) || !(prm->alpha_max < 1.f))
+    return fail(QR_ERR_INVALID_ARG, "%s: need 0 < alpha_min <= alpha_max < 1", name);
+  if (!(prm->T_eps >= 0.f)) return fail(QR_ERR_INVALID_ARG, "%s: T_eps must be >= 0", name);
+  if (prm->out_dtype != QR_F32) return fail(QR_ERR_UNSUPPORTED, "%s: float32 output only", name);
+  if (n_items == 0) return QR_OK;
+  hipStream_t s = as_stream(stream);
+  const int64_t n_units = n_items * kStrips;
+  if (n_workgroups == 0) {
+    const int nu = static_cast<int>(n_units);
+#define QR_LAUNCH(DT)                                                                          \
+  hipLaunchKernelGGL(render_dense_batched_grid_kernel<DT>, dim3(nu), dim3(kTilePix), 0, s, views, \
+                     schedule, nu, dim, *prm)
+    QR_DENSE_DISPATCH(dtype);
+#undef QR_LAUNCH
+    return check_launch(name);
+  }
+  auto* counter = static_cast<uint32_t*>(workspace);
+  hipLaunchKernelGGL(reset_dense_counter_kernel, dim3(1), dim3(64), 0, s, counter);
+#define QR_LAUNCH(DT)                                                                           \
+  hipLaunchKernelGGL(render_dense_batched_kernel<DT>, dim3(n_workgroups), dim3(kTilePix), 0, s,   \
+                     views, schedule, n_units, counter, dim, *prm)
+  QR_DENSE_DISPATCH(dtype);
+#undef QR_LAUNCH
+  return check_launch(name);
 }

@@ -179,3 +179,55 @@ def test_reduced_batched_workload_fp8_forward_and_backward(qr):
                 worst = float((a64 - b64).abs().max() / b64.abs().max())
                 assert rel <= 1e-5 and worst <= 1e-5, (kind, w, si, rel, worst)
         del got
+
+
+def test_room_batched_dense_matches_single_view_and_oracle(qr):
+    """The dense blend over the same 16 room poses, items and launch shapes
+    as the batched Q-Render launch the benchmark times: bit-identical to the
+    single-view dense kernel per pose; two poses' maps against the oracle on
+    sampled tiles (with the longest list)."""
+    from paper_2512_20927_amd import _lib as L
+    from paper_2512_20927_amd.batched import BatchedDense
+    cfg = synth.CONFIGS["room"]
+    W, H, D = cfg["width"], cfg["height"], cfg["dim"]
+    sc = synth.make_room(cfg["n"], cfg["seed"], dim=D)
+    cams = synth.room_poses(cfg["pose_seeds"], W, H, cfg["fx"])
+    st = _scene_t(sc)
+    feats = _t(sc.features)
+    pv, vb = _front(qr, st, cams, W, H)
+    per_view = [vb.view(pv, v) for v in range(len(cams))]
+    views = [_view(pr, b, feats, None, W, H, D) for pr, b in per_view]
+    bd = BatchedDense(views, D, L.QR_F32, qr.RenderParams().c())
+    for kind, w in SHAPES:
+        print("room batched dense launch", kind, w, flush=True)
+        for v in views:
+            v["out"].fill_(float("nan"))
+            v["T_q"].fill_(float("nan"))
+            v["n_sel"].fill_(-7)
+        bd.render(kind, w)
+        for i, (pr, b) in enumerate(per_view):
+            ref = qr.render_dense(pr, b, feats, W, H)
+            torch.cuda.synchronize()
+            assert torch.equal(views[i]["out"], ref["out"]), (kind, w, i)
+            assert torch.equal(views[i]["T_q"], ref["T_final"]), (kind, w, i)
+            assert torch.equal(views[i]["n_sel"], ref["n_contrib"]), (kind, w, i)
+            del ref
+    for i in (0, 7):
+        pr, b = per_view[i]
+        offs = b.tile_offsets.cpu().numpy().astype(np.int64)
+        lo = int(offs[0])
+        gids = b.sorted_gid[lo:int(offs[-1])].cpu().numpy().astype(np.int64)
+        offs = offs - lo
+        lens = np.diff(offs)
+        rng = np.random.default_rng(60 + i)
+        tiles = [int(np.argmax(lens))] + [int(t) for t in rng.choice(np.nonzero(lens > 0)[0], 4, replace=False)]
+        proj = proj_for_oracle(dict(means2d=pr.means2d.cpu().numpy(), conic_opacity=pr.conic_opacity.cpu().numpy()))
+        ors = [oracle.render_dense(proj, gids, offs, sc.features, W, H, tiles=tiles, bias=bb)
+               for bb in (0.0, DECISION_WINDOW, -DECISION_WINDOW)]
+        ev = ~np.isnan(ors[0]["out"][..., 0])
+        st_ = compare_render(views[i]["out"].cpu().numpy(), ors[0], ors[1:], evaluated=ev)
+        clean = ev & (ors[0]["margin"] > DECISION_WINDOW)
+        np.testing.assert_array_equal(views[i]["n_sel"].cpu().numpy()[clean], ors[0]["n_contrib"][clean])
+        np.testing.assert_allclose(views[i]["T_q"].cpu().numpy()[clean], ors[0]["T_final"][clean],
+                                   rtol=1e-4, atol=1e-7)
+        print("dense pose", i, "tiles", tiles, st_)
