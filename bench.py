@@ -273,7 +273,106 @@ def _tile_err(gpu_map, ref, tiles, W, H):
             "max_clean": float(e[c].max()) if c.any() else 0.0, "clean": int(c.sum())}
 
 
-def cpu_reference(sc, cam, K, budget_s, gpu_q=None, gpu_d=None, label="room pose 100"):
+def view_records(pr, b):
+    """Host copies of one view's projected records and tile lists (the GPU's
+    own float32 values): the oracle renders exactly the lists the GPU did."""
+    offs = b.tile_offsets.cpu().numpy().astype(np.int64)
+    lo = int(offs[0])
+    co = pr.conic_opacity.cpu().numpy().astype(np.float64)
+    return dict(means2d=pr.means2d.cpu().numpy().astype(np.float64), conic=co[:, :3],
+                opacity=co[:, 3], gids=b.sorted_gid[lo:int(offs[-1])].cpu().numpy().astype(np.int64),
+                offs=offs - lo)
+
+
+def sample_tiles(offs, n, seed):
+    """The tile with the longest list and n - 1 other non-empty tiles."""
+    lens = np.diff(offs)
+    rng = np.random.default_rng(seed)
+    nz = np.nonzero(lens > 0)[0]
+    heavy = int(np.argmax(lens))
+    rest = rng.choice(nz[nz != heavy], min(n - 1, len(nz) - 1), replace=False)
+    return [heavy] + [int(t) for t in rest]
+
+
+def gather_tiles(t_map, tiles, W, H):
+    """[len(tiles), 16, 16, D] host copy of the given tiles of a GPU map
+    (pixels outside the image NaN)."""
+    import torch
+    tx = (W + 15) // 16
+    out = np.full((len(tiles), 16, 16, t_map.shape[-1]), np.nan, np.float32)
+    for i, t in enumerate(tiles):
+        y0, x0 = (t // tx) * 16, (t % tx) * 16
+        blk = t_map[y0:y0 + 16, x0:x0 + 16].float().cpu().numpy()
+        out[i, :blk.shape[0], :blk.shape[1]] = blk
+    return out
+
+
+def oracle_tile(rec, t, feats, W, H, K=None):
+    """The oracle's render of one tile of a view as a standalone image of
+    that tile: records shifted by the tile origin (an exact shift: the pixel
+    offsets px + 0.5 - u are the same numbers), the tile's list alone. K
+    None: the dense blend."""
+    import oracle
+    tx = (W + 15) // 16
+    y0, x0 = (t // tx) * 16, (t % tx) * 16
+    w, h = min(16, W - x0), min(16, H - y0)
+    lo, hi = int(rec["offs"][t]), int(rec["offs"][t + 1])
+    gids = rec["gids"][lo:hi]
+    uniq, local = np.unique(gids, return_inverse=True)
+    proj = dict(means2d=rec["means2d"][uniq] - np.array([x0, y0], np.float64),
+                conic=rec["conic"][uniq], opacity=rec["opacity"][uniq])
+    f = np.asarray(feats[uniq], np.float64)
+    offs = np.array([0, hi - lo], np.int64)
+    if K is None:
+        return oracle.render_dense(proj, local.astype(np.int64), offs, f, w, h)
+    return oracle.render_quantile(proj, local.astype(np.int64), offs, f, w, h, K)
+
+
+def tile_errors(gpu_tiles, refs):
+    """Per-pixel relative L2 error over sampled tiles: all pixels, and those
+    whose decisions lie more than 1e-4 (relative) from their boundaries."""
+    errs, clean = [], []
+    for g, r in zip(gpu_tiles, refs):
+        h, w = r["out"].shape[:2]
+        gg = g[:h, :w].astype(np.float64)
+        e = np.linalg.norm(gg - r["out"], axis=-1) / np.maximum(np.linalg.norm(r["out"], axis=-1), 1e-6)
+        errs.append(e.ravel())
+        clean.append((r["margin"] > 1e-4).ravel())
+    e, c = np.concatenate(errs), np.concatenate(clean)
+    return {"pixels": int(e.size), "max": float(e.max()), "p99": float(np.percentile(e, 99)),
+            "mean": float(e.mean()), "over_1e-2": int((e > 1e-2).sum()),
+            "max_clean": float(e[c].max()) if c.any() else 0.0, "clean": int(c.sum())}
+
+
+class RowSubset:
+    """Rows of a feature table for a sorted subset of Gaussian ids, indexed
+    by Gaussian id (what oracle_tile takes from a full table)."""
+
+    def __init__(self, ids, rows):
+        self.ids, self.rows = ids, rows
+
+    def __getitem__(self, idx):
+        return self.rows[np.searchsorted(self.ids, idx)]
+
+
+def storage_errors(records, tiles, gpu_tiles, decoded, original, W, H, K=None):
+    """Kernel error (the oracle on the decoded stored values: what the kernel
+    computes, float32 against float64) and storage error (the oracle on the
+    original float32 features: what the reduced storage costs) of GPU maps
+    of sampled tiles of several views."""
+    out = {}
+    for name, feats in (("kernel", decoded), ("storage", original)):
+        refs, gts = [], []
+        for rec, tl, gt in zip(records, tiles, gpu_tiles):
+            for i, t in enumerate(tl):
+                refs.append(oracle_tile(rec, t, feats, W, H, K))
+                gts.append(gt[i])
+        out[name] = tile_errors(gts, refs)
+    return out
+
+
+def cpu_reference(sc, cam, K, budget_s, gpu_q=None, gpu_d=None, label="room pose 100",
+                  max_workers=16):
     """The FP64 oracle pipeline on this host: projection and binning of the
     whole scene, then Algorithm 1 on an evenly spaced random sample of tiles
     sized to the time budget, on one core and then split over a fork pool on
@@ -318,7 +417,8 @@ def cpu_reference(sc, cam, K, budget_s, gpu_q=None, gpu_d=None, label="room pose
         limiter.unregister()
 
     # the same sample over a pool of forked workers, one BLAS thread each
-    cores = _host_cores()
+    # (each oracle call holds a float64 frame, so large frames take fewer workers)
+    cores = min(_host_cores(), max_workers)
     frame_all, t_pool = None, None
     if cores > 1:
         _CPU_SHARED.update(pr=pr, gids=gids, offs=offs, feats=feats, W=cam.width, H=cam.height, K=K)
@@ -605,7 +705,7 @@ def run_precision(args):
     s = _scene_tensors(sc, torch)
     f32 = torch.from_numpy(sc.features).cuda()
     s["feats"], _ = qr.quantize(f32, "bf16")
-    del f32, sc
+    del f32
     pv = qr.project_views(s["means"], s["scales"], s["quats"], s["opacity"], cams)
     capacity = int(qr.count_pairs(pv) * 1.05) + 1024
     del pv
@@ -619,6 +719,11 @@ def run_precision(args):
         st.front()
     torch.cuda.synchronize()
     pairs = [int(b.tile_offsets[-1].item() - b.tile_offsets[0].item()) for _, b in states[0].per_view]
+    check = args.cpu_budget > 0 and not args.renders_only
+    if check:  # sampled tiles of every view, checked against the oracle after timing
+        records = [view_records(pr, b) for pr, b in states[0].per_view]
+        tiles = [sample_tiles(r["offs"], 4, 90 + v) for v, r in enumerate(records)]
+    gpu_tiles = {}
     per_k, render_ms, tuned_k = {}, {}, {}
     frames = args.steps * nv
     for K in cfg["Ks"]:
@@ -629,8 +734,27 @@ def run_precision(args):
         per_k[str(K)] = round(frames / dt, 2)
         render_ms[str(K)] = round(kms, 4)
         tuned_k[str(K)] = {k: tuned[k] for k in ("schedule", "wg_per_cu")}
+        if check:
+            torch.cuda.synchronize()
+            gpu_tiles[K] = [gather_tiles(outs[v], tiles[v], W, H) for v in range(nv)]
     dt_d, k_d, tuned_d, _ = timed_dense(states, args.steps, args.warmup)
     d_fps = frames / dt_d
+    errors = cpu = None
+    if check:
+        torch.cuda.synchronize()
+        gpu_tiles["dense"] = [gather_tiles(outs[v], tiles[v], W, H) for v in range(nv)]
+        decoded = s["feats"].float().cpu().numpy()  # bf16 -> f32 is exact
+        errors = {"reference": "FP64 oracle on the GPU's own projected records and tile lists, "
+                               "4 sampled tiles per view (the longest list among them); kernel: "
+                               "oracle on the decoded bf16 values; storage: oracle on the original "
+                               "float32 features"}
+        for key in list(cfg["Ks"]) + ["dense"]:
+            errors["K=%d" % key if key != "dense" else "dense"] = storage_errors(
+                records, tiles, gpu_tiles[key], decoded, sc.features, W, H,
+                None if key == "dense" else key)
+        del decoded
+        cpu, _ = cpu_reference(sc, cams[0], 8, args.cpu_budget, label="precision pose 200",
+                               max_workers=8)
     rec = _base_record(args, per_k["8"], "frames/s", "bf16",
                        "precision: 1M Gaussians, 1296x968, fx=fy=1168.4, 512-D bf16 features "
                        "(float32 accumulation), 4 poses per step; value = Q-Render K=8",
@@ -641,6 +765,7 @@ def run_precision(args):
                               "dense_batched_launch": round(k_d, 4)},
                 "batched_launch_per_K": tuned_k,
                 "dense_batched_launch": {k: tuned_d[k] for k in ("schedule", "wg_per_cu")},
+                "error_vs_oracle": errors, "cpu_baseline": cpu,
                 "workload_stats": {"pairs_mean": float(np.mean(pairs))}})
     print(json.dumps(rec))
 
@@ -836,11 +961,15 @@ def run_batched(args):
     prm_c = qr.RenderParams().c()
     scenes, fronts = [], []
     seed = 300
-    for n, sd in zip(sizes, seeds):
+    check = args.cpu_budget > 0 and not args.renders_only
+    originals = {}  # float32 features of the scenes whose views are checked
+    for si, (n, sd) in enumerate(zip(sizes, seeds)):
         sc = synth.make_room(n, sd, dim=D)
         st = _scene_tensors(sc, torch)
         f32 = torch.from_numpy(sc.features).cuda()
         st["codes"], st["scale"] = qr.quantize(f32, "fp8")
+        if check and si in (0, len(sizes) - 1):
+            originals[si] = sc.features
         del f32, sc
         scenes.append(st)
         cams = [synth.room_camera(seed + k, W, H, 1154.0) for k in range(per)]
@@ -883,6 +1012,34 @@ def run_batched(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     render_ms = float(np.mean([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(args.steps)]))
+    errors = None
+    if check:
+        # kernel and storage error of two timed views (smallest and largest
+        # scene) on sampled tiles against the FP64 oracle
+        errors = {"reference": "FP64 oracle on the GPU's own projected records and tile lists, "
+                               "6 sampled tiles of view 0 (0.3M scene) and of view 24 (3M scene), "
+                               "the longest list among them; kernel: oracle on the decoded e4m3 "
+                               "values times their scale; storage: oracle on the original float32 "
+                               "features"}
+        recs, tls, gts, dec, org = [], [], [], [], []
+        for vi in (0, n_views - per):
+            si, prv, bv = per_view[vi]
+            rec = view_records(prv, bv)
+            tl = sample_tiles(rec["offs"], 6, 70 + vi)
+            ids = np.unique(np.concatenate([rec["gids"][rec["offs"][t]:rec["offs"][t + 1]] for t in tl]))
+            idt = torch.from_numpy(ids).cuda()
+            codes = scenes[si]["codes"][idt]
+            rows = (codes.view(torch.float8_e4m3fn).float() * scenes[si]["scale"][idt][:, None]).cpu().numpy()
+            recs.append(rec)
+            tls.append(tl)
+            gts.append(gather_tiles(outs[vi], tl, W, H))
+            dec.append(RowSubset(ids, rows))
+            org.append(RowSubset(ids, originals[si][ids]))
+        errors["K=%d" % K] = {name: tile_errors(
+            [g[i] for g, tl in zip(gts, tls) for i in range(len(tl))],
+            [oracle_tile(r, t, f, W, H, K) for r, tl, f in zip(recs, tls, feats) for t in tl])
+            for name, feats in (("kernel", dec), ("storage", org))}
+        del originals
     # backward of all 32 views in one launch over the same items (views of a
     # scene accumulate into the scene's gradient arrays); one grad_out buffer
     # serves every view
@@ -913,7 +1070,8 @@ def run_batched(args):
                 "autotuned": {k: tuned[k] for k in ("schedule", "wg_per_cu")},
                 "autotune_ms": {k: round(v, 3) for k, v in timings.items()},
                 "backward_ms_per_batch": {k: round(v, 3) for k, v in bwd_ms.items()},
-                "backward_views_per_s": round(n_views / (best_bwd * 1e-3), 2)})
+                "backward_views_per_s": round(n_views / (best_bwd * 1e-3), 2),
+                "error_vs_oracle": errors})
     print(json.dumps(rec))
 
 

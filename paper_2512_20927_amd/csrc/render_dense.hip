@@ -40,6 +40,7 @@
 namespace qr {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kStripRows = 4;                      // tile rows per strip
 constexpr int kStripPix = kTile * kStripRows;      // 64: one pixel per lane
@@ -60,7 +61,7 @@ struct DenseLds {
   // ids of the batch, double-buffered by batch parity: the second column
   // group's loads read them after the last barrier of the batch, while wave
   // 0 may already be staging the next batch
-  int gid[2][kDB];
+  __attribute__((aligned(16))) uint32_t gid[2][kDB];
   float part[4][kStripPix];   // product of (1 - alpha') over a wave's eight entries
   float tend[4][kStripPix];   // T after a wave's eight entries (before its stop)
   uint32_t info[4][kStripPix];  // last blended entry (0..7, 0xFF none) | kStopBit
@@ -75,13 +76,18 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
 // Four consecutive features (d .. d+3) of row g as raw loads: float32 values,
 // or bfloat16 codes in the low 8 bytes.
 template <int DT>
-__device__ __forceinline__ f32x4 load_raw4(const GView& v, int g, int dim, int d) {
-  if constexpr (DT == QR_BF16) {
+__device__ __forceinline__ f32x4 load_raw4(const GView& v, uint32_t g, int dim, int d) {
+  const uint64_t off = static_cast<uint64_t>(g) * static_cast<uint32_t>(dim) + static_cast<uint32_t>(d);
+  if constexpr (DT == QR_F32) {
+    return *reinterpret_cast<const QR_GLOBAL f32x4*>(static_cast<const QR_GLOBAL float*>(v.feats) + off);
+  } else if constexpr (DT == QR_BF16) {
     const u32x2 r = *reinterpret_cast<const QR_GLOBAL u32x2*>(
-        static_cast<const QR_GLOBAL uint16_t*>(v.feats) + static_cast<int64_t>(g) * dim + d);
+        static_cast<const QR_GLOBAL uint16_t*>(v.feats) + off);
     return f32x4{__uint_as_float(r.x), __uint_as_float(r.y), 0.f, 0.f};
   } else {
-    const float4 x = load_feat4_global<DT>(v.feats, v.scale, g, dim, d);
+    const uint32_t r = *reinterpret_cast<const QR_GLOBAL uint32_t*>(
+        static_cast<const QR_GLOBAL uint8_t*>(v.feats) + off);
+    const float4 x = e4m3x4_to_f32(r, v.scale[g]);
     return f32x4{x.x, x.y, x.z, x.w};
   }
 }
@@ -110,6 +116,12 @@ __device__ void dense_strip(const GView& v, int tile, int strip, int dim, const 
   const int hi = static_cast<int>(v.tile_offsets[tile + 1]);
   const int coff = 16 * (ci & 3) + 4 * (ci >> 2);  // the lane's columns in a group
   int par = 0;  // parity of the batches staged so far (selects the id buffer)
+  // The next batch's ids and records are requested by threads 0..31 while
+  // the current batch is contracted, and staged into LDS at the top of the
+  // next iteration.
+  int rgid = -1;
+  f32x2 rmean = f32x2{0.f, 0.f};
+  f32x4 rco = f32x4{0.f, 0.f, 0.f, 0.f};
 
   for (int c0 = 0; c0 < dim; c0 += kPassCols) {
     // this wave's column groups in the pass: base column and width (0: none)
@@ -130,37 +142,45 @@ __device__ void dense_strip(const GView& v, int tile, int strip, int dim, const 
 #pragma unroll
         for (int p = 0; p < 4; ++p) acc[k][c][p] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // the pixel states are identical in every wave: uniform exits
+    const bool first = lo < hi && __ballot(!done) != 0ull;  // uniform
+    if (first && tid < kDB && lo + tid < hi) {
+      rgid = static_cast<int>(v.sorted_gid[lo + tid]);
+      rmean = v.means2d[rgid];
+      rco = v.conic_opacity[rgid];
+    }
     for (int batch = lo; batch < hi; batch += kDB) {
-      // the pixel states are identical in every wave: a uniform exit
       if (__ballot(!done) == 0ull) break;
       const int cnt = min(kDB, hi - batch);
+      const int nb = batch + kDB;
       // records of the batch (the previous batch's were last read before the
       // second barrier of its iteration, which every wave has passed; its ids
       // are in the other buffer)
-      int* const gid = L.gid[par];
+      uint32_t* const gid = L.gid[par];
       par ^= 1;
+      // every id slot holds a valid row: slots past the list repeat the
+      // batch's first id (their weights are zero)
+      const int g0 = __shfl(rgid, 0);
+      if (tid < kDB) gid[tid] = static_cast<uint32_t>(tid < cnt ? rgid : g0);
       if (tid < cnt) {
-        const int g = static_cast<int>(v.sorted_gid[batch + tid]);
-        gid[tid] = g;
-        const f32x2 m = v.means2d[g];
-        const f32x4 c = v.conic_opacity[g];
-        L.mean[tid] = make_float2(m.x, m.y);
-        L.co[tid] = make_float4(c.x, c.y, c.z, c.w);
+        L.mean[tid] = make_float2(rmean.x, rmean.y);
+        L.co[tid] = make_float4(rco.x, rco.y, rco.z, rco.w);
       }
       __syncthreads();
 
       // feature rows of the batch for this wave's first group, requested now
       // so that the loads overlap the walk (the second group's are requested
-      // before the first group's MFMAs)
+      // before the first group's MFMAs). No branches: ids past the list are
+      // valid rows (weight 0), and columns past the width of a partial group
+      // are clamped to its first (their results are never stored).
       f32x4 raw[8];
       const auto load_group = [&](int k) {
-        const bool use = coff < gw[k];
+        const int col = gbase[k] + (coff < gw[k] ? coff : 0);
+        const u32x4 ga = *reinterpret_cast<const u32x4*>(&gid[8 * kb]);
+        const u32x4 gb = *reinterpret_cast<const u32x4*>(&gid[8 * kb + 4]);
+        const uint32_t g8[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int e = 8 * kb + t;
-          raw[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-          if (use && e < cnt) raw[t] = load_raw4<DT>(v, gid[e], dim, gbase[k] + coff);
-        }
+        for (int t = 0; t < 8; ++t) raw[t] = load_raw4<DT>(v, g8[t], dim, col);
       };
       load_group(0);
 
@@ -235,12 +255,23 @@ __device__ void dense_strip(const GView& v, int tile, int strip, int dim, const 
         }
       }
       const unsigned long long busy = L.busy[0] | L.busy[1] | L.busy[2] | L.busy[3];
+      // the next batch's ids (its records are requested after the first
+      // group's MFMAs, once the ids have arrived)
+      const bool more = nb < hi && __ballot(!done) != 0ull;  // uniform: another batch follows
+      const bool prefetch = more && tid < kDB && nb + tid < hi;
+      if (prefetch) rgid = static_cast<int>(v.sorted_gid[nb + tid]);
 
       // F^T W^T on the matrix cores, one column group at a time: A = this
       // wave's features (rows permuted within the group), B = the weights of
       // 16 pixels
 #pragma unroll
       for (int k = 0; k < kWaveGroups; ++k) {
+        if (k == 1 && prefetch) {
+          // the next batch's records (their ids, requested before the first
+          // group's MFMAs, have arrived)
+          rmean = v.means2d[rgid];
+          rco = v.conic_opacity[rgid];
+        }
         if (gw[k] == 0) continue;
         bf16x8 ahi[4], alo[4];
 #pragma unroll
@@ -279,20 +310,45 @@ __device__ void dense_strip(const GView& v, int tile, int strip, int dim, const 
 
     // results: lane (kb, ci) holds, for pixel row p of the strip and column
     // tile c, out^T rows 4 kb + r (r = 0..3), i.e. columns 16 r + 4 kb + c of
-    // pixel ci: four consecutive columns per (r, p)
+    // pixel ci: four consecutive columns per (r, p). A 128-byte line of a
+    // pixel (32 columns, r = 2m and 2m + 1) is spread over 8 lanes and two
+    // values; lanes ci and ci ^ 8 swap one value (DPP rotation by 8 within
+    // each row of 16 lanes), so that each store instruction writes whole
+    // lines: 8 pixels x 128 bytes. (With 64-byte pieces the memory side read
+    // back and rewrote half lines: about 1.5x the map's bytes.)
+    const bool left = ci < 8;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      const int ox = tx * kTile + ci, oy = ty * kTile + strip * kStripRows + p;
-      if (ox >= W || oy >= H) continue;
-      QR_GLOBAL float* dst = v.out + (static_cast<int64_t>(oy) * W + ox) * dim;
+      const int oy = ty * kTile + strip * kStripRows + p;
+      const int xa = tx * kTile + (left ? ci : ci - 8);  // pixel of the first store
+      const int xb = xa + 8;                              // of the second
+      const int64_t rowpix = static_cast<int64_t>(oy) * W;
 #pragma unroll
       for (int k = 0; k < kWaveGroups; ++k) {
+        if (gw[k] == 0) continue;  // uniform over the wave
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int col = 16 * r + 4 * kb;
-          if (col < gw[k])
-            store_stream(reinterpret_cast<QR_GLOBAL float4*>(dst + gbase[k] + col),
-                         make_float4(acc[k][0][p][r], acc[k][1][p][r], acc[k][2][p][r], acc[k][3][p][r]));
+        for (int m = 0; m < 2; ++m) {
+          float lo4[4], hi4[4], a4[4], b4[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            lo4[c] = acc[k][c][p][2 * m];
+            hi4[c] = acc[k][c][p][2 * m + 1];
+            const float send = left ? hi4[c] : lo4[c];
+            const float recv = __int_as_float(
+                __builtin_amdgcn_mov_dpp(__float_as_int(send), 0x128, 0xF, 0xF, false));
+            a4[c] = left ? lo4[c] : recv;
+            b4[c] = left ? recv : hi4[c];
+          }
+          const int col = 32 * m + (left ? 0 : 16) + 4 * kb;
+          if (oy < H && col < gw[k]) {
+            QR_GLOBAL float* base = v.out + gbase[k] + col;
+            if (xa < W)
+              store_stream(reinterpret_cast<QR_GLOBAL float4*>(base + (rowpix + xa) * dim),
+                           make_float4(a4[0], a4[1], a4[2], a4[3]));
+            if (xb < W)
+              store_stream(reinterpret_cast<QR_GLOBAL float4*>(base + (rowpix + xb) * dim),
+                           make_float4(b4[0], b4[1], b4[2], b4[3]));
+          }
         }
       }
     }

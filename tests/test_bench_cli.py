@@ -25,3 +25,30 @@ def test_every_listed_workload_is_dispatched():
     assert {"room", "rgb", "devox", "batched", "diff", "precision"} <= set(names)
     for n in names:
         assert re.search(r'"%s": run_%s\b' % (n, n), src), n
+
+
+def test_oracle_tile_equals_the_full_frame_render():
+    """bench.oracle_tile renders one tile as its own image with the records
+    shifted by the tile origin; that must be exactly the full-frame render of
+    the tile (ragged edge tiles included)."""
+    import numpy as np
+    import bench
+    import oracle
+    import synth
+    sc, cam = synth.make_tiny(3, n=800, dim=16), synth.tiny_camera(40)
+    cam.height, cam.cy = 37, 18.5
+    pr = oracle.project(sc.means, sc.scales, sc.quats, sc.opacity, cam)
+    tx, ty = 3, 3
+    gids, offs, _ = oracle.bin_sort(pr["rect"], pr["depth"], tx, ty)
+    rec = dict(means2d=pr["means2d"], conic=pr["conic"], opacity=pr["opacity"], gids=gids, offs=offs)
+    full_q = oracle.render_quantile(pr, gids, offs, sc.features, 40, 37, 8)
+    full_d = oracle.render_dense(pr, gids, offs, sc.features, 40, 37)
+    for t in range(tx * ty):
+        y0, x0 = (t // tx) * 16, (t % tx) * 16
+        q = bench.oracle_tile(rec, t, sc.features, 40, 37, 8)
+        d = bench.oracle_tile(rec, t, sc.features, 40, 37)
+        h, w = q["out"].shape[:2]
+        assert (h, w) == (min(16, 37 - y0), min(16, 40 - x0))
+        np.testing.assert_array_equal(q["out"], full_q["out"][y0:y0 + h, x0:x0 + w])
+        np.testing.assert_array_equal(q["margin"], full_q["margin"][y0:y0 + h, x0:x0 + w])
+        np.testing.assert_array_equal(d["out"], full_d["out"][y0:y0 + h, x0:x0 + w])
