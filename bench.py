@@ -217,14 +217,14 @@ def dense_list_prefix(b, n_contrib, W, H):
     return total, int(torch.unique(b.sorted_gid[idx]).numel())
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, family="render_quantile"):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE passes, calibrated by a 1 GiB copy), or None when
     there is none or the kernel's sources changed since it was taken."""
     from paper_2512_20927_amd import profile_summary as ps
     name = kernel.split("<")[0].replace("_kernel", "")
     info = ps.read_summary(os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (name, workload)))
-    if not info or info.get("source_sha256") != ps.source_hash("render_quantile"):
+    if not info or info.get("source_sha256") != ps.source_hash(family):
         return None
     return int(info["traffic_bytes_per_launch"])
 
@@ -662,6 +662,7 @@ def run_room(args):
                   "roofline": {"bound": "hbm", "kernel": kernel_d, "achieved": round(achieved_d, 1),
                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": round(achieved_d / HBM_PEAK_GBS, 4),
+                               "traffic": measured_traffic(kernel_d, "room", "render_dense"),
                                "bytes_per_launch": round(bytes_d)},
                   "list_prefix_pairs_mean": float(np.mean(pairs_d)),
                   "blended_unique_mean": float(np.mean(uniq_d))},

@@ -38,6 +38,10 @@ KERNEL_SOURCES = {
                         "paper_2512_20927_amd/csrc/quantile_select.h",
                         "paper_2512_20927_amd/csrc/render_common.h",
                         "paper_2512_20927_amd/csrc/common.h"],
+    "render_dense": ["paper_2512_20927_amd/csrc/render_dense.hip",
+                     "paper_2512_20927_amd/csrc/quantile_select.h",
+                     "paper_2512_20927_amd/csrc/render_common.h",
+                     "paper_2512_20927_amd/csrc/common.h"],
 }
 
 COPY_BYTES = 1 << 30
