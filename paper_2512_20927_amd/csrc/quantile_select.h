@@ -27,27 +27,39 @@ constexpr uint32_t kTileMask = (1u << QR_BATCH_TILE_BITS) - 1u;
 
 constexpr int kPG = 4;                     // pixels gathered together
 constexpr int kGroups = kTilePix / kPG;    // 64 pixel groups per tile
-#ifndef QR_UCAP
-#define QR_UCAP 16
-#endif
-constexpr int kUCap = QR_UCAP;             // distinct selections kept per group
+// Distinct selections kept per merged group: 16, or 32 for 24 < K <= 52,
+// where the selection lists already hold the kernel to one workgroup per CU
+// (at K = 40 about 44% of the room workload's groups have more than 16
+// distinct selections and 0.1% more than 32).
+constexpr int kUCap = 16;
+constexpr int kUCapLarge = 32;
+constexpr int kUCapLargeMinK = 25;
+constexpr int kUCapLargeMaxK = 52;
+__host__ __device__ constexpr int ucap_for(int K) {
+  return K >= kUCapLargeMinK && K <= kUCapLargeMaxK ? kUCapLarge : kUCap;
+}
 // Three 45 KB workgroups fill a CU's LDS: registers are bounded to match
 // (three waves per SIMD).
 constexpr int kWavesPerSimd = 3;
 
 // LDS of one workgroup: record staging, thresholds, per-pixel scalars and
-// the merged groups (each pixel's [K] selections live in dynamic LDS).
-struct QuantileLds {
+// the merged groups of up to UCAP distinct selections (each pixel's [K]
+// selections live in dynamic LDS).
+template <int UCAP>
+struct QuantileLdsT {
+  static constexpr int kCap = UCAP;
   float2 mean[kTilePix];
   float4 co[kTilePix];
   float thr[QR_MAX_K + 1];
+  double zq[QR_MAX_K];                     // Stratified-K: z_m, m = 1..K
   float inv[kTilePix];
   int ns[kTilePix];
-  int unum[kGroups];                       // distinct entries per group, -1 if over kUCap
-  int ugid[kGroups * kUCap];               // a group's distinct selections (list positions until converted)
-  float4 uw[kGroups * kUCap];              // their weights for the group's four pixels, x = first pixel
-  uint8_t umask[kGroups * kUCap];          // bit q: pixel q of the group selected the entry
+  int unum[kGroups];                       // distinct entries per group, -1 if over UCAP
+  int ugid[kGroups * UCAP];                // a group's distinct selections (list positions until converted)
+  float4 uw[kGroups * UCAP];               // their weights for the group's four pixels, x = first pixel
+  uint8_t umask[kGroups * UCAP];           // bit q: pixel q of the group selected the entry
 };
+using QuantileLds = QuantileLdsT<kUCap>;
 
 struct ViewArgs {
   int W, H;
@@ -135,6 +147,10 @@ __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi
   const int tid = threadIdx.x;
   // thr[k] = t_{k+1}; thr[K] = 0 (identical for every tile of a launch)
   if (MODE == QR_SELECT_QUANTILE && tid <= K) L.thr[tid] = quantile_threshold(tid + 1, K);
+  if constexpr (MODE == QR_SELECT_STRATIFIED) {
+    if (tid < K) L.zq[tid] = stratified_z(tid + 1, K);  // read after the barrier below
+    __syncthreads();
+  }
   const float amin = prm.alpha_min, amax = prm.alpha_max;
 
   double mu = 0.0, sigma = 0.0;
@@ -187,8 +203,8 @@ __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi
     mu = s1 / n;
     sigma = sqrt(fmax(s2 / n - mu * mu, 0.0));
   }
-  auto threshold = [&](int kk) -> float {  // t_{kk+1}
-    if constexpr (MODE == QR_SELECT_STRATIFIED) return stratified_threshold(kk + 1, K, mu, sigma);
+  auto threshold = [&](int kk) -> float {  // t_{kk+1}; past t_K none is crossed
+    if constexpr (MODE == QR_SELECT_STRATIFIED) return kk < K ? stratified_threshold_z(L.zq[kk], mu, sigma) : -1.f;
     else return L.thr[kk];
   };
 
@@ -196,8 +212,9 @@ __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi
   int k = 0, ns = 0, last = 0;
   bool done = !inside;
   // t_{k+1}: changes only at a crossing
-  float thr_k = MODE == QR_SELECT_STRATIFIED ? stratified_threshold(1, K, mu, sigma)
-                                             : quantile_threshold(1, K);
+  float thr_k;
+  if constexpr (MODE == QR_SELECT_STRATIFIED) thr_k = threshold(0);
+  else thr_k = quantile_threshold(1, K);
   int* my_pos = s_sel_pos + tid * KP;
   float* my_w = s_sel_w + tid * KP;
   float wmin = 0.f;  // Top-K: the worst kept entry (smallest weight, later position among equals)
@@ -320,9 +337,11 @@ __device__ __forceinline__ PixelSel quantile_walk(const GView& v, int lo, int hi
 }
 
 // The merge for one tile (all 256 threads; wave-local), after the walk.
-__device__ __forceinline__ void merge_groups(const GView& v, QuantileLds& L,
+template <class Lds>
+__device__ __forceinline__ void merge_groups(const GView& v, Lds& L,
                                              const int* __restrict__ s_sel_pos,
                                              const float* __restrict__ s_sel_w, int KP) {
+  constexpr int kCap = Lds::kCap;
   const int tid = threadIdx.x;
   // The merge, wave-local: adjacent pixels select mostly the same
   // Gaussians, so a group's distinct selections are far fewer than its
@@ -349,7 +368,7 @@ __device__ __forceinline__ void merge_groups(const GView& v, QuantileLds& L,
     for (;;) {
       const int best = min(min(head[0], head[1]), min(head[2], head[3]));
       if (best == 0x7fffffff) break;
-      if (cnt == kUCap) {
+      if (cnt == kCap) {
         cnt = -1;
         break;
       }
@@ -366,31 +385,36 @@ __device__ __forceinline__ void merge_groups(const GView& v, QuantileLds& L,
           hw[q] = idx[q] < n[q] ? s_sel_w[(p0 + q) * KP + idx[q]] * inv[q] : 0.f;
         }
       }
-      L.ugid[grp * kUCap + cnt] = best;  // position for now
-      L.uw[grp * kUCap + cnt] = make_float4(wq[0], wq[1], wq[2], wq[3]);
-      L.umask[grp * kUCap + cnt] = static_cast<uint8_t>(mk);
+      L.ugid[grp * kCap + cnt] = best;  // position for now
+      L.uw[grp * kCap + cnt] = make_float4(wq[0], wq[1], wq[2], wq[3]);
+      L.umask[grp * kCap + cnt] = static_cast<uint8_t>(mk);
       ++cnt;
     }
     L.unum[grp] = cnt;
-    // positions -> Gaussian ids: all loads issued before any result is used
-    int pos[kUCap];
+    // positions -> Gaussian ids, 16 at a time: all loads of a batch issued
+    // before any result is used
 #pragma unroll
-    for (int e = 0; e < kUCap; ++e) pos[e] = e < cnt ? L.ugid[grp * kUCap + e] : -1;
-    uint32_t gid[kUCap];
+    for (int e0 = 0; e0 < kCap; e0 += 16) {
+      if (e0 >= cnt) break;
+      int pos[16];
 #pragma unroll
-    for (int e = 0; e < kUCap; ++e) gid[e] = pos[e] >= 0 ? v.sorted_gid[pos[e]] : 0u;
+      for (int e = 0; e < 16; ++e) pos[e] = e0 + e < cnt ? L.ugid[grp * kCap + e0 + e] : -1;
+      uint32_t gid[16];
 #pragma unroll
-    for (int e = 0; e < kUCap; ++e)
-      if (e < cnt) L.ugid[grp * kUCap + e] = static_cast<int>(gid[e]);
+      for (int e = 0; e < 16; ++e) gid[e] = pos[e] >= 0 ? v.sorted_gid[pos[e]] : 0u;
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        if (e0 + e < cnt) L.ugid[grp * kCap + e0 + e] = static_cast<int>(gid[e]);
+    }
   }
   wave_lds_sync();
 }
 
 // Walk and merge (the forward renderer's selection phase).
-template <int MODE>
+template <int MODE, class Lds>
 __device__ __forceinline__ PixelSel quantile_select(const GView& v, int lo, int hi, int K,
                                                     float pxc, float pyc, bool inside,
-                                                    const qr_params& prm, QuantileLds& L,
+                                                    const qr_params& prm, Lds& L,
                                                     int* __restrict__ s_sel_pos,
                                                     float* __restrict__ s_sel_w, int KP) {
   const PixelSel sel = quantile_walk<MODE>(v, lo, hi, K, pxc, pyc, inside, prm, L, s_sel_pos, s_sel_w, KP);

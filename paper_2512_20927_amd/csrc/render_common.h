@@ -26,12 +26,15 @@ __device__ __forceinline__ float quantile_threshold(int m, int K) {
   return static_cast<float>(1.0 - static_cast<double>(m) / static_cast<double>(K + 1));
 }
 
-// Stratified-K threshold t_m = clip(mu + sigma Phi^-1(1 - m/(K+1)), 0, 1) in
-// double, rounded once to float; m = K+1 gives -1, which no transmittance
-// crosses.
-__device__ __forceinline__ float stratified_threshold(int m, int K, double mu, double sigma) {
-  if (m > K) return -1.f;
-  const double t = mu + sigma * normcdfinv(1.0 - static_cast<double>(m) / static_cast<double>(K + 1));
+// Stratified-K threshold t_m = clip(mu + sigma z_m, 0, 1) with
+// z_m = Phi^-1(1 - m/(K+1)), in double, rounded once to float. z_m depends on
+// m and K only, so the walk computes it once per tile (stratified_z) and
+// forms t_m per ray from it.
+__device__ __forceinline__ double stratified_z(int m, int K) {
+  return normcdfinv(1.0 - static_cast<double>(m) / static_cast<double>(K + 1));
+}
+__device__ __forceinline__ float stratified_threshold_z(double z, double mu, double sigma) {
+  const double t = mu + sigma * z;
   return static_cast<float>(fmin(fmax(t, 0.0), 1.0));
 }
 

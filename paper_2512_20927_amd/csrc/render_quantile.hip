@@ -79,14 +79,14 @@ __device__ __forceinline__ void store_out4(QR_GLOBAL float* out, int64_t pix, in
 // the merged weights). Each lane owns two float4 columns per pass (512
 // features per pass for the wave); rows are taken four at a time, the last
 // two or one on their own, so no multiply is spent on padding.
-template <int DT, int OT>
-__device__ __forceinline__ void gather_group_merged(const GView& v, const QuantileLds& L, int grp,
+template <int DT, int OT, class Lds>
+__device__ __forceinline__ void gather_group_merged(const GView& v, const Lds& L, int grp,
                                                     int nu, int tx, int ty, int lane, int dim) {
   const int dim4 = dim >> 2;
   const int p0 = grp * kPG;
-  const int* ug = &L.ugid[grp * kUCap];
-  const float4* uw = &L.uw[grp * kUCap];
-  const uint8_t* um = &L.umask[grp * kUCap];
+  const int* ug = &L.ugid[grp * Lds::kCap];
+  const float4* uw = &L.uw[grp * Lds::kCap];
+  const uint8_t* um = &L.umask[grp * Lds::kCap];
   for (int cb = 0; cb < dim4; cb += 128) {
     const int c0 = cb + lane, c1 = cb + 64 + lane;
     const int l0 = min(c0, dim4 - 1), l1 = min(c1, dim4 - 1);  // in-bounds columns to load
@@ -118,13 +118,15 @@ __device__ __forceinline__ void gather_group_merged(const GView& v, const Quanti
 // Gather-blend of all sixteen merged groups of a wave at once, for narrow
 // rows (dim <= 128): lpg lanes per group (the power of two >= dim / 4, one
 // float4 column each), so 64 / lpg groups are blended side by side, and all
-// kUCap row loads of a lane are requested before the first is used (slots
-// past a group's distinct count load a row of the group again and are not
-// accumulated). One memory round trip per round instead of one per group.
-// Groups with more than kUCap distinct selections are skipped here.
-template <int DT, int OT>
-__device__ __forceinline__ void gather_groups_narrow(const GView& v, const QuantileLds& L, int wave,
+// kUCap (16) row loads of a lane are requested before the first is used
+// (slots past a group's distinct count load a row of the group again and are
+// not accumulated). One memory round trip per round instead of one per
+// group. Groups with more than kUCap distinct selections (also under the
+// larger merge capacity) are skipped here.
+template <int DT, int OT, class Lds>
+__device__ __forceinline__ void gather_groups_narrow(const GView& v, const Lds& L, int wave,
                                                      int tx, int ty, int lane, int dim) {
+  constexpr int kCap = Lds::kCap;
   const int dim4 = dim >> 2;
   const int lpg_log = dim4 <= 4 ? 2 : dim4 <= 8 ? 3 : dim4 <= 16 ? 4 : 5;
   const int gpr = 64 >> lpg_log;  // groups per round
@@ -133,12 +135,13 @@ __device__ __forceinline__ void gather_groups_narrow(const GView& v, const Quant
   constexpr int kWaveGroups = kGroups / 4;
   for (int r0 = 0; r0 < kWaveGroups; r0 += gpr) {
     const int grp = wave * kWaveGroups + r0 + (lane >> lpg_log);
-    const int nu = L.unum[grp];
+    const int nu_all = L.unum[grp];
+    const int nu = nu_all > kUCap ? -1 : nu_all;  // more than kUCap: the overflow path
     float4 a[kPG];
 #pragma unroll
     for (int q = 0; q < kPG; ++q) a[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (nu > 0) {
-      const int* ug = &L.ugid[grp * kUCap];
+      const int* ug = &L.ugid[grp * kCap];
       float4 f[kUCap];
 #pragma unroll
       for (int e = 0; e < kUCap; ++e)
@@ -146,7 +149,7 @@ __device__ __forceinline__ void gather_groups_narrow(const GView& v, const Quant
 #pragma unroll
       for (int e = 0; e < kUCap; ++e) {
         if (e < nu) {
-          const float4 w = L.uw[grp * kUCap + e];
+          const float4 w = L.uw[grp * kCap + e];
           const float ws[kPG] = {w.x, w.y, w.z, w.w};
 #pragma unroll
           for (int q = 0; q < kPG; ++q) {
@@ -172,11 +175,11 @@ __device__ __forceinline__ void gather_groups_narrow(const GView& v, const Quant
 }
 
 // The groups that gather_groups_narrow skipped (more than kUCap distinct
-// selections), with the same lane layout: pixel by pixel, each pixel's
+// selections, or than the merge capacity), with the same lane layout: pixel by pixel, each pixel's
 // selections taken eight at a time (their ids, then their rows, each batch
 // requested together), all such groups of a round side by side.
-template <int DT, int OT>
-__device__ __forceinline__ void gather_groups_narrow_overflow(const GView& v, const QuantileLds& L,
+template <int DT, int OT, class Lds>
+__device__ __forceinline__ void gather_groups_narrow_overflow(const GView& v, const Lds& L,
                                                               const int* __restrict__ s_sel_pos,
                                                               const float* __restrict__ s_sel_w,
                                                               int KP, int K, int wave, int tx, int ty,
@@ -190,7 +193,7 @@ __device__ __forceinline__ void gather_groups_narrow_overflow(const GView& v, co
   constexpr int kWaveGroups = kGroups / 4;
   for (int r0 = 0; r0 < kWaveGroups; r0 += gpr) {
     const int grp = wave * kWaveGroups + r0 + (lane >> lpg_log);
-    const bool mine = L.unum[grp] < 0;
+    const bool mine = L.unum[grp] < 0 || L.unum[grp] > kUCap;
     if (!__any(mine)) continue;
 #pragma unroll 1
     for (int q = 0; q < kPG; ++q) {
@@ -232,10 +235,10 @@ __device__ __forceinline__ void gather_groups_narrow_overflow(const GView& v, co
   }
 }
 
-// Gather-blend of a group with more than kUCap distinct selections: pixel
-// by pixel, each selection's row loaded for its own pixel.
-template <int DT, int OT>
-__device__ __forceinline__ void gather_group_per_pixel(const GView& v, const QuantileLds& L,
+// Gather-blend of a group with more distinct selections than the merge
+// capacity: pixel by pixel, each selection's row loaded for its own pixel.
+template <int DT, int OT, class Lds>
+__device__ __forceinline__ void gather_group_per_pixel(const GView& v, const Lds& L,
                                                        const int* __restrict__ s_sel_pos,
                                                        const float* __restrict__ s_sel_w, int KP,
                                                        int grp, int tx, int ty, int lane, int dim) {
@@ -292,9 +295,9 @@ __device__ __forceinline__ void gather_group_per_pixel(const GView& v, const Qua
 // gather groups it owns, so everything after the walk is wave-local.
 // Shared LDS (the record batch) is only rewritten after a barrier that every
 // wave reaches once it has finished the previous tile.
-template <int DT, int OT, int MODE>
+template <int DT, int OT, int MODE, class Lds>
 __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, int dim,
-                                              const qr_params& prm, QuantileLds& L,
+                                              const qr_params& prm, Lds& L,
                                               int* __restrict__ s_sel_gid,
                                               float* __restrict__ s_sel_w,
                                               int32_t* __restrict__ sel_gid_out,
@@ -331,7 +334,7 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
       const int nu = __builtin_amdgcn_readfirstlane(L.unum[grp]);
       if (nu >= 0)
         gather_group_merged<DT, OT>(v, L, grp, nu, tx, ty, lane, dim);
-      else  // more distinct selections than kUCap (rare)
+      else  // more distinct selections than the merge capacity (rare)
         gather_group_per_pixel<DT, OT>(v, L, s_sel_pos, s_sel_w, KP, grp, tx, ty, lane, dim);
     }
   }
@@ -353,13 +356,13 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
   }
 }
 
-template <int DT, int OT, int MODE>
+template <int DT, int OT, int MODE, int UCAP>
 __global__ void __launch_bounds__(kTilePix, kWavesPerSimd)
 render_quantile_kernel(ViewArgs v, int n_tiles, qr_params prm, int K, int dim,
                        int32_t* __restrict__ sel_gid_out, float* __restrict__ sel_w_out,
                        float* __restrict__ T_final_out, int32_t* __restrict__ last_pos_out) {
   extern __shared__ unsigned char dyn_lds[];
-  __shared__ QuantileLds L;
+  __shared__ QuantileLdsT<UCAP> L;
   int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);                            // [256][KP]
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);  // [256][KP]
   quantile_tile<DT, OT, MODE>(to_global(v), xcd_remap(blockIdx.x, n_tiles), K, dim, prm, L, s_sel_gid,
@@ -378,13 +381,13 @@ __device__ __forceinline__ uint32_t queue_begin(int64_t n_items, int q) {
   return static_cast<uint32_t>(n_items * q / kXcdQueues);
 }
 
-template <int DT, int OT, int MODE>
+template <int DT, int OT, int MODE, int UCAP>
 __global__ void __launch_bounds__(kTilePix, kWavesPerSimd)
 render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t* __restrict__ schedule,
                                int64_t n_items, uint32_t* __restrict__ counter, qr_params prm,
                                int K, int dim) {
   extern __shared__ unsigned char dyn_lds[];
-  __shared__ QuantileLds L;
+  __shared__ QuantileLdsT<UCAP> L;
   __shared__ uint32_t s_item[2];
   int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);
@@ -422,13 +425,13 @@ render_quantile_batched_kernel(const qr_view* __restrict__ views, const uint32_t
 // dealt to the XCDs in contiguous runs of the schedule (neighbouring tiles of
 // a view share L2 contents); workgroups retire as they finish, so work on
 // other streams can take their slots.
-template <int DT, int OT, int MODE>
+template <int DT, int OT, int MODE, int UCAP>
 __global__ void __launch_bounds__(kTilePix, kWavesPerSimd)
 render_quantile_batched_grid_kernel(const qr_view* __restrict__ views,
                                     const uint32_t* __restrict__ schedule, int n_items,
                                     qr_params prm, int K, int dim) {
   extern __shared__ unsigned char dyn_lds[];
-  __shared__ QuantileLds L;
+  __shared__ QuantileLdsT<UCAP> L;
   int* s_sel_gid = reinterpret_cast<int*>(dyn_lds);
   float* s_sel_w = reinterpret_cast<float*>(dyn_lds) + kTilePix * ((K + 3) & ~3);
   const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[xcd_remap(blockIdx.x, n_items)]);
@@ -445,26 +448,26 @@ __global__ void reset_counter_kernel(uint32_t* __restrict__ c) {
 
 using namespace qr;
 
-// Instantiates QR_LAUNCH(feature dtype, output dtype, selection rule) for the
-// runtime triple.
-#define QR_DISPATCH_DT(dt, OT, SM)                        \
-  switch (dt) {                                           \
-    case QR_F32: QR_LAUNCH(QR_F32, OT, SM); break;        \
-    case QR_BF16: QR_LAUNCH(QR_BF16, OT, SM); break;      \
-    default: QR_LAUNCH(QR_FP8_E4M3, OT, SM); break;       \
+// Instantiates QR_LAUNCH(feature dtype, output dtype, selection rule, merge
+// capacity) for the runtime values; the larger merge capacity is built for
+// float32 maps (bfloat16 maps keep 16, which is correct at any K).
+#define QR_DISPATCH_DT(dt, OT, SM, UC)                        \
+  switch (dt) {                                               \
+    case QR_F32: QR_LAUNCH(QR_F32, OT, SM, UC); break;        \
+    case QR_BF16: QR_LAUNCH(QR_BF16, OT, SM, UC); break;      \
+    default: QR_LAUNCH(QR_FP8_E4M3, OT, SM, UC); break;       \
   }
-#define QR_DISPATCH(dt, ot, sm)                                                   \
-  do {                                                                            \
-    if ((sm) == QR_SELECT_TOPK) {                                                 \
-      if ((ot) == QR_BF16) { QR_DISPATCH_DT(dt, QR_BF16, QR_SELECT_TOPK) }       \
-      else { QR_DISPATCH_DT(dt, QR_F32, QR_SELECT_TOPK) }                        \
-    } else if ((sm) == QR_SELECT_STRATIFIED) {                                    \
-      if ((ot) == QR_BF16) { QR_DISPATCH_DT(dt, QR_BF16, QR_SELECT_STRATIFIED) } \
-      else { QR_DISPATCH_DT(dt, QR_F32, QR_SELECT_STRATIFIED) }                  \
-    } else {                                                                      \
-      if ((ot) == QR_BF16) { QR_DISPATCH_DT(dt, QR_BF16, QR_SELECT_QUANTILE) }   \
-      else { QR_DISPATCH_DT(dt, QR_F32, QR_SELECT_QUANTILE) }                    \
-    }                                                                             \
+#define QR_DISPATCH_OT(dt, ot, SM, K)                                                   \
+  do {                                                                                  \
+    if ((ot) == QR_BF16) { QR_DISPATCH_DT(dt, QR_BF16, SM, kUCap) }                     \
+    else if (ucap_for(K) == kUCapLarge) { QR_DISPATCH_DT(dt, QR_F32, SM, kUCapLarge) }  \
+    else { QR_DISPATCH_DT(dt, QR_F32, SM, kUCap) }                                      \
+  } while (0)
+#define QR_DISPATCH(dt, ot, sm, K)                                                  \
+  do {                                                                              \
+    if ((sm) == QR_SELECT_TOPK) QR_DISPATCH_OT(dt, ot, QR_SELECT_TOPK, K);          \
+    else if ((sm) == QR_SELECT_STRATIFIED) QR_DISPATCH_OT(dt, ot, QR_SELECT_STRATIFIED, K); \
+    else QR_DISPATCH_OT(dt, ot, QR_SELECT_QUANTILE, K);                             \
   } while (0)
 
 extern "C" int qr_render_quantile(void* stream, int32_t width, int32_t height,
@@ -493,10 +496,10 @@ extern "C" int qr_render_quantile(void* stream, int32_t width, int32_t height,
   const ViewArgs v{width, height, tile_offsets, sorted_gid, reinterpret_cast<const float2*>(means2d),
                    reinterpret_cast<const float4*>(conic_opacity), features, feature_scale, out, T_q,
                    n_sel};
-#define QR_LAUNCH(DT, OT, SM)                                                                         \
-  hipLaunchKernelGGL((render_quantile_kernel<DT, OT, SM>), dim3(n_tiles), dim3(kTilePix), lds, s, v,    \
+#define QR_LAUNCH(DT, OT, SM, UC)                                                                     \
+  hipLaunchKernelGGL((render_quantile_kernel<DT, OT, SM, UC>), dim3(n_tiles), dim3(kTilePix), lds, s, v, \
                      n_tiles, *prm, K, dim, sel_gid, sel_w, T_final, last_pos)
-  QR_DISPATCH(dtype, prm->out_dtype, prm->selection);
+  QR_DISPATCH(dtype, prm->out_dtype, prm->selection, K);
 #undef QR_LAUNCH
   return check_launch("qr_render_quantile");
 }
@@ -534,19 +537,19 @@ extern "C" int qr_render_quantile_batched(void* stream, int32_t n_views, const q
   const size_t lds = static_cast<size_t>(kTilePix) * ((K + 3) & ~3) * (sizeof(int) + sizeof(float));
   if (n_workgroups == 0) {
     const int ni = static_cast<int>(n_items);
-#define QR_LAUNCH(DT, OT, SM)                                                                         \
-  hipLaunchKernelGGL((render_quantile_batched_grid_kernel<DT, OT, SM>), dim3(ni), dim3(kTilePix), lds, \
+#define QR_LAUNCH(DT, OT, SM, UC)                                                                     \
+  hipLaunchKernelGGL((render_quantile_batched_grid_kernel<DT, OT, SM, UC>), dim3(ni), dim3(kTilePix), lds, \
                      s, views, schedule, ni, *prm, K, dim)
-    QR_DISPATCH(dtype, prm->out_dtype, prm->selection);
+    QR_DISPATCH(dtype, prm->out_dtype, prm->selection, K);
 #undef QR_LAUNCH
     return check_launch("qr_render_quantile_batched");
   }
   auto* counter = static_cast<uint32_t*>(workspace);
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
-#define QR_LAUNCH(DT, OT, SM)                                                                         \
-  hipLaunchKernelGGL((render_quantile_batched_kernel<DT, OT, SM>), dim3(n_workgroups), dim3(kTilePix),  \
+#define QR_LAUNCH(DT, OT, SM, UC)                                                                     \
+  hipLaunchKernelGGL((render_quantile_batched_kernel<DT, OT, SM, UC>), dim3(n_workgroups), dim3(kTilePix), \
                      lds, s, views, schedule, n_items, counter, *prm, K, dim)
-  QR_DISPATCH(dtype, prm->out_dtype, prm->selection);
+  QR_DISPATCH(dtype, prm->out_dtype, prm->selection, K);
 #undef QR_LAUNCH
   return check_launch("qr_render_quantile_batched");
 }
