@@ -557,8 +557,9 @@ def run_room(args):
     # bracket the batched launch alone (in the overlapped run the front of the
     # next step shares the GPU with it)
     achieved = bytes_batch / (k_seq * 1e-3) / 1e9
-    kernel = ("render_quantile_batched_grid_kernel<0, 0, 0>" if tuned["wg_per_cu"] == 0
-              else "render_quantile_batched_kernel<0, 0, 0>")
+    ucap = 32 if 25 <= K <= 52 else 16  # the kernels' merge capacity for this K
+    kernel = ("render_quantile_batched_grid_kernel<0, 0, 0, %d>" % ucap if tuned["wg_per_cu"] == 0
+              else "render_quantile_batched_kernel<0, 0, 0, %d>" % ucap)
     traffic = measured_traffic(kernel, "room")
     # the dense launch: the same output and per-pixel scalars, the records of
     # each tile's list up to its last blended entry, each blended Gaussian's

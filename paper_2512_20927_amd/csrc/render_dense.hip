@@ -33,6 +33,8 @@
 //     overlap it; 16-pixel rows of the strip that take nothing from a batch
 //     skip their MFMAs; the strip leaves the list once all 64 pixels stopped.
 // Widths above 512 are rendered in passes of 512 columns, each walking again.
+// Widths up to 64 take the tile kernels further down (dense_tile_narrow):
+// one workgroup per tile, one sequential walk per pixel, one barrier per batch.
 #include "common.h"
 #include "quantile_select.h"
 #include "render_common.h"
@@ -92,13 +94,104 @@ __device__ __forceinline__ f32x4 load_raw4(const GView& v, uint32_t g, int dim, 
   }
 }
 
+// A operands (bfloat16 pairs) of one column group from its raw rows: column
+// tile c takes component c of the lane's eight rows.
+template <int DT>
+__device__ __forceinline__ void convert_group(const f32x4 (&raw)[8], bf16x8 (&ahi)[4],
+                                              bf16x8 (&alo)[4]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if constexpr (DT != QR_BF16) {
+        __bf16 h, l;
+        split_bf16(raw[t][c], h, l);
+        ahi[c][t] = h;
+        alo[c][t] = l;
+      } else {
+        // bfloat16 codes: two per 32-bit word, column c in word c / 2
+        const uint32_t word = __float_as_uint(raw[t][c >> 1]);
+        const uint16_t code = static_cast<uint16_t>((c & 1) ? (word >> 16) : (word & 0xFFFFu));
+        ahi[c][t] = __builtin_bit_cast(__bf16, code);
+      }
+    }
+  }
+}
+
+// acc[c][p] += F^T W^T for one column group (4 column tiles) and the 4 pixel
+// rows of 16 of a strip whose weights (bfloat16 pairs, row stride kWS) are at
+// whi / wlo; pixel rows with no weight in `busy` are skipped.
+template <int DT>
+__device__ __forceinline__ void mfma_group(f32x4 (&acc)[4][4], const bf16x8 (&ahi)[4],
+                                           const bf16x8 (&alo)[4], const __bf16* whi,
+                                           const __bf16* wlo, unsigned long long busy, int ci,
+                                           int kb) {
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    if (((busy >> (16 * p)) & 0xFFFFull) == 0ull) continue;
+    const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(&whi[(16 * p + ci) * kWS + 8 * kb]);
+    const bf16x8 blo = *reinterpret_cast<const bf16x8*>(&wlo[(16 * p + ci) * kWS + 8 * kb]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      acc[c][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[c], bhi, acc[c][p], 0, 0, 0);
+      acc[c][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[c], blo, acc[c][p], 0, 0, 0);
+      if constexpr (DT != QR_BF16)
+        acc[c][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[c], bhi, acc[c][p], 0, 0, 0);
+    }
+  }
+}
+
+// Stores one column group (columns gbase .. gbase + gw) of a strip's 64
+// pixels. Lane (kb, ci) holds, for pixel row p of the strip and column tile
+// c, out^T rows 4 kb + r (r = 0..3), i.e. columns 16 r + 4 kb + c of pixel
+// ci: four consecutive columns per (r, p). A 128-byte line of a pixel (32
+// columns, r = 2m and 2m + 1) is spread over 8 lanes and two values; lanes ci
+// and ci ^ 8 swap one value (DPP rotation by 8 within each row of 16 lanes),
+// so that each store instruction writes whole lines: 8 pixels x 128 bytes.
+// (With 64-byte pieces the memory side read back and rewrote half lines:
+// about 1.5x the map's bytes.) Called by every lane of the wave.
+__device__ __forceinline__ void store_group(const GView& v, const f32x4 (&acc)[4][4], int tx,
+                                            int ty, int strip, int gbase, int gw, int dim, int ci,
+                                            int kb) {
+  const bool left = ci < 8;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int oy = ty * kTile + strip * kStripRows + p;
+    const int xa = tx * kTile + (left ? ci : ci - 8);  // pixel of the first store
+    const int xb = xa + 8;                              // of the second
+    const int64_t rowpix = static_cast<int64_t>(oy) * v.W;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      float a4[4], b4[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float lo4 = acc[c][p][2 * m], hi4 = acc[c][p][2 * m + 1];
+        const float send = left ? hi4 : lo4;
+        const float recv = __int_as_float(
+            __builtin_amdgcn_mov_dpp(__float_as_int(send), 0x128, 0xF, 0xF, false));
+        a4[c] = left ? lo4 : recv;
+        b4[c] = left ? recv : hi4;
+      }
+      const int col = 32 * m + (left ? 0 : 16) + 4 * kb;
+      if (oy < v.H && col < gw) {
+        QR_GLOBAL float* base = v.out + gbase + col;
+        if (xa < v.W)
+          store_stream(reinterpret_cast<QR_GLOBAL float4*>(base + (rowpix + xa) * dim),
+                       make_float4(a4[0], a4[1], a4[2], a4[3]));
+        if (xb < v.W)
+          store_stream(reinterpret_cast<QR_GLOBAL float4*>(base + (rowpix + xb) * dim),
+                       make_float4(b4[0], b4[1], b4[2], b4[3]));
+      }
+    }
+  }
+}
+
 // One 64-pixel strip of one tile: Eq. 1 for its pixels, all `dim` columns.
 // Called by all 256 threads; every barrier is reached by every wave the same
 // number of times (loop bounds and exits are uniform over the workgroup).
 template <int DT>
 __device__ void dense_strip(const GView& v, int tile, int strip, int dim, const qr_params& prm,
                             DenseLds& L) {
-  constexpr bool kSplitF = DT != QR_BF16;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -274,89 +367,232 @@ __device__ void dense_strip(const GView& v, int tile, int strip, int dim, const 
         }
         if (gw[k] == 0) continue;
         bf16x8 ahi[4], alo[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            if constexpr (kSplitF) {
-              __bf16 h, l;
-              split_bf16(raw[t][c], h, l);
-              ahi[c][t] = h;
-              alo[c][t] = l;
-            } else {
-              // bfloat16 codes: two per 32-bit word, column c in word c / 2
-              const uint32_t word = __float_as_uint(raw[t][c >> 1]);
-              const uint16_t code = static_cast<uint16_t>((c & 1) ? (word >> 16) : (word & 0xFFFFu));
-              ahi[c][t] = __builtin_bit_cast(__bf16, code);
-            }
-          }
-        }
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          if (((busy >> (16 * p)) & 0xFFFFull) == 0ull) continue;
-          const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(&L.whi[(16 * p + ci) * kWS + 8 * kb]);
-          const bf16x8 blo = *reinterpret_cast<const bf16x8*>(&L.wlo[(16 * p + ci) * kWS + 8 * kb]);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            acc[k][c][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[c], bhi, acc[k][c][p], 0, 0, 0);
-            acc[k][c][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[c], blo, acc[k][c][p], 0, 0, 0);
-            if constexpr (kSplitF)
-              acc[k][c][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[c], bhi, acc[k][c][p], 0, 0, 0);
-          }
-        }
+        convert_group<DT>(raw, ahi, alo);
+        mfma_group<DT>(acc[k], ahi, alo, L.whi, L.wlo, busy, ci, kb);
         if (k + 1 < kWaveGroups) load_group(k + 1);
       }
     }
 
-    // results: lane (kb, ci) holds, for pixel row p of the strip and column
-    // tile c, out^T rows 4 kb + r (r = 0..3), i.e. columns 16 r + 4 kb + c of
-    // pixel ci: four consecutive columns per (r, p). A 128-byte line of a
-    // pixel (32 columns, r = 2m and 2m + 1) is spread over 8 lanes and two
-    // values; lanes ci and ci ^ 8 swap one value (DPP rotation by 8 within
-    // each row of 16 lanes), so that each store instruction writes whole
-    // lines: 8 pixels x 128 bytes. (With 64-byte pieces the memory side read
-    // back and rewrote half lines: about 1.5x the map's bytes.)
-    const bool left = ci < 8;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int oy = ty * kTile + strip * kStripRows + p;
-      const int xa = tx * kTile + (left ? ci : ci - 8);  // pixel of the first store
-      const int xb = xa + 8;                              // of the second
-      const int64_t rowpix = static_cast<int64_t>(oy) * W;
-#pragma unroll
-      for (int k = 0; k < kWaveGroups; ++k) {
-        if (gw[k] == 0) continue;  // uniform over the wave
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          float lo4[4], hi4[4], a4[4], b4[4];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            lo4[c] = acc[k][c][p][2 * m];
-            hi4[c] = acc[k][c][p][2 * m + 1];
-            const float send = left ? hi4[c] : lo4[c];
-            const float recv = __int_as_float(
-                __builtin_amdgcn_mov_dpp(__float_as_int(send), 0x128, 0xF, 0xF, false));
-            a4[c] = left ? lo4[c] : recv;
-            b4[c] = left ? recv : hi4[c];
-          }
-          const int col = 32 * m + (left ? 0 : 16) + 4 * kb;
-          if (oy < H && col < gw[k]) {
-            QR_GLOBAL float* base = v.out + gbase[k] + col;
-            if (xa < W)
-              store_stream(reinterpret_cast<QR_GLOBAL float4*>(base + (rowpix + xa) * dim),
-                           make_float4(a4[0], a4[1], a4[2], a4[3]));
-            if (xb < W)
-              store_stream(reinterpret_cast<QR_GLOBAL float4*>(base + (rowpix + xb) * dim),
-                           make_float4(b4[0], b4[1], b4[2], b4[3]));
-          }
-        }
-      }
-    }
+    for (int k = 0; k < kWaveGroups; ++k)
+      if (gw[k] > 0) store_group(v, acc[k], tx, ty, strip, gbase[k], gw[k], dim, ci, kb);
     if (c0 == 0 && wave == 0 && inside) {
       const int pix = py * W + px;
       if (v.T_q) v.T_q[pix] = T;
       if (v.n_sel) v.n_sel[pix] = ncon;
     }
+  }
+}
+
+// Narrow features (dim <= 64: one column group). The strip decomposition
+// above splits each batch's walk over four waves and pays three barriers and a
+// cross-wave fold per batch for it; with one column group there is little
+// MFMA work to hide that behind. Here one workgroup takes a whole tile: wave w
+// owns strip w (tile rows 4w .. 4w + 3), each lane walks its pixel's chain
+// over all 32 entries of a batch in list order (the transmittance recursion
+// of Eq. 1 exactly as written, no reassociation), writes its weights to the
+// wave's own LDS rows and the wave contracts them with the batch's feature
+// rows. Records are double-buffered, so one barrier per batch both publishes
+// the staged records and tests whether any pixel of the tile is still live.
+struct DenseNarrowLds {
+  __attribute__((aligned(16))) __bf16 whi[4][kStripPix * kWS];
+  __attribute__((aligned(16))) __bf16 wlo[4][kStripPix * kWS];
+  float2 mean[2][kDB];
+  float4 co[2][kDB];
+  __attribute__((aligned(16))) uint32_t gid[2][kDB];
+};
+
+// One column of row g (dim == 16 layout): float32 value, or the bfloat16 code
+// in the low half.
+template <int DT>
+__device__ __forceinline__ float load_raw1(const GView& v, uint32_t g, int d) {
+  const uint64_t off = static_cast<uint64_t>(g) * 16u + static_cast<uint32_t>(d);
+  if constexpr (DT == QR_F32) {
+    return static_cast<const QR_GLOBAL float*>(v.feats)[off];
+  } else if constexpr (DT == QR_BF16) {
+    return __uint_as_float(static_cast<const QR_GLOBAL uint16_t*>(v.feats)[off]);
+  } else {
+    const uint32_t r = static_cast<const QR_GLOBAL uint8_t*>(v.feats)[off];
+    return __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(r), false)[0] * v.scale[g];
+  }
+}
+
+// kOne: dim == 16, one MFMA column tile in natural order (row i = column i);
+// a lane loads its column of eight entries and stores four consecutive
+// columns of one pixel, and a store instruction covers 16 whole pixels (1 KB
+// contiguous). Otherwise (16 < dim <= 64) one permuted column group as in the
+// strip kernel.
+template <int DT, bool kOne>
+__device__ void dense_tile_narrow(const GView& v, int tile, int dim, const qr_params& prm,
+                                  DenseNarrowLds& L) {
+  constexpr int NC = kOne ? 1 : 4;  // MFMA column tiles
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int kb = lane >> 4;
+  const int ci = lane & 15;
+  const int W = v.W, H = v.H;
+  const int tiles_x = (W + kTile - 1) / kTile;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  // the lane's pixel: row kb, column ci of the wave's strip (so that its
+  // weights are row `lane` of the wave's B operand)
+  const int px = tx * kTile + ci;
+  const int py = ty * kTile + wave * kStripRows + kb;
+  const bool inside = px < W && py < H;
+  const float pxc = px + 0.5f, pyc = py + 0.5f;
+  const int lo = static_cast<int>(v.tile_offsets[tile]);
+  const int hi = static_cast<int>(v.tile_offsets[tile + 1]);
+  // permuted layout: the lane's four columns (clamped to the group's first
+  // past the width: loaded, never stored)
+  const int coff = 16 * (ci & 3) + 4 * (ci >> 2);
+  const int col = coff < dim ? coff : 0;
+  __bf16* const whi = L.whi[wave];
+  __bf16* const wlo = L.wlo[wave];
+
+  float T = 1.f;
+  bool done = !inside;
+  int ncon = 0;
+  f32x4 acc[NC][4];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) acc[c][p] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // records of the next batch, requested by threads 0..31 one batch ahead
+  int rgid = -1;
+  f32x2 rmean = f32x2{0.f, 0.f};
+  f32x4 rco = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (tid < kDB && lo + tid < hi) {
+    rgid = static_cast<int>(v.sorted_gid[lo + tid]);
+    rmean = v.means2d[rgid];
+    rco = v.conic_opacity[rgid];
+  }
+  int par = 0;
+  for (int batch = lo; batch < hi; batch += kDB, par ^= 1) {
+    const int cnt = min(kDB, hi - batch);
+    const int nb = batch + kDB;
+    // stage the batch into buffer `par` (its previous contents, two batches
+    // back, were last read before the previous iteration's barrier); id
+    // slots past the list repeat the batch's first id (weight 0)
+    const int g0 = __shfl(rgid, 0);
+    if (tid < kDB) {
+      L.gid[par][tid] = static_cast<uint32_t>(tid < cnt ? rgid : g0);
+      L.mean[par][tid] = make_float2(rmean.x, rmean.y);
+      L.co[par][tid] = make_float4(rco.x, rco.y, rco.z, rco.w);
+    }
+    // publishes the records; uniform exit once every pixel has stopped
+    if (__syncthreads_count(!done) == 0) break;
+    const bool prefetch = tid < kDB && nb + tid < hi;
+    if (prefetch) rgid = static_cast<int>(v.sorted_gid[nb + tid]);
+    if (__ballot(!done) == 0ull) {  // uniform per wave: its strip has finished
+      if (prefetch) {
+        rmean = v.means2d[rgid];
+        rco = v.conic_opacity[rgid];
+      }
+      continue;
+    }
+
+    // the batch's feature rows (ids past the list are valid rows), requested
+    // before the walk so that the loads overlap it
+    const u32x4 ga = *reinterpret_cast<const u32x4*>(&L.gid[par][8 * kb]);
+    const u32x4 gb = *reinterpret_cast<const u32x4*>(&L.gid[par][8 * kb + 4]);
+    const uint32_t g8[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+    f32x4 raw[kOne ? 1 : 8];
+    float raw1[kOne ? 8 : 1];
+    if constexpr (kOne) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) raw1[t] = load_raw1<DT>(v, g8[t], ci);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) raw[t] = load_raw4<DT>(v, g8[t], dim, col);
+    }
+
+    // Eq. 1 along the lane's ray, in list order
+    bool any = false;
+#pragma unroll 1
+    for (int q = 0; q < kDB / 8; ++q) {
+      bf16x8 bh, bl;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = 8 * q + j;
+        float w = 0.f;
+        if (e < cnt && !done) {
+          const float a = gauss_alpha(L.mean[par][e], L.co[par][e], pxc, pyc, prm.alpha_max);
+          if (a >= prm.alpha_min) {
+            const float T_test = T * (1.f - a);
+            if (T_test < prm.T_eps) {
+              done = true;
+            } else {
+              w = a * T;
+              T = T_test;
+              ncon = batch - lo + e + 1;
+            }
+          }
+        }
+        any |= w != 0.f;
+        __bf16 h, l;
+        split_bf16(w, h, l);
+        bh[j] = h;
+        bl[j] = l;
+      }
+      *reinterpret_cast<bf16x8*>(&whi[lane * kWS + 8 * q]) = bh;
+      *reinterpret_cast<bf16x8*>(&wlo[lane * kWS + 8 * q]) = bl;
+    }
+    if (prefetch) {
+      rmean = v.means2d[rgid];
+      rco = v.conic_opacity[rgid];
+    }
+    const unsigned long long busy = __ballot(any);
+    wave_lds_sync();  // the wave's weights, written by all its lanes
+    if (busy == 0ull) continue;
+    if constexpr (kOne) {
+      bf16x8 ahi, alo;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if constexpr (DT != QR_BF16) {
+          __bf16 h, l;
+          split_bf16(raw1[t], h, l);
+          ahi[t] = h;
+          alo[t] = l;
+        } else {
+          ahi[t] = __builtin_bit_cast(__bf16, static_cast<uint16_t>(__float_as_uint(raw1[t])));
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        if (((busy >> (16 * p)) & 0xFFFFull) == 0ull) continue;
+        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(&whi[(16 * p + ci) * kWS + 8 * kb]);
+        const bf16x8 blo = *reinterpret_cast<const bf16x8*>(&wlo[(16 * p + ci) * kWS + 8 * kb]);
+        acc[0][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[0][p], 0, 0, 0);
+        acc[0][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[0][p], 0, 0, 0);
+        if constexpr (DT != QR_BF16)
+          acc[0][p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[0][p], 0, 0, 0);
+      }
+    } else {
+      bf16x8 ahi[4], alo[4];
+      convert_group<DT>(raw, ahi, alo);
+      mfma_group<DT>(acc, ahi, alo, whi, wlo, busy, ci, kb);
+    }
+  }
+
+  if constexpr (kOne) {
+    // lane (kb, ci) holds columns 4 kb .. 4 kb + 3 of pixel ci of row p
+    const int ox = tx * kTile + ci;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int oy = ty * kTile + wave * kStripRows + p;
+      if (ox < W && oy < H)
+        store_stream(reinterpret_cast<QR_GLOBAL float4*>(
+                         v.out + (static_cast<int64_t>(oy) * W + ox) * 16 + 4 * kb),
+                     make_float4(acc[0][p][0], acc[0][p][1], acc[0][p][2], acc[0][p][3]));
+    }
+  } else {
+    store_group(v, acc, tx, ty, wave, 0, dim, dim, ci, kb);
+  }
+  if (inside) {
+    const int pix = py * W + px;
+    if (v.T_q) v.T_q[pix] = T;
+    if (v.n_sel) v.n_sel[pix] = ncon;
   }
 }
 
@@ -425,6 +661,59 @@ render_dense_batched_kernel(const qr_view* __restrict__ views, const uint32_t* _
   }
 }
 
+// The narrow-feature kernels: one workgroup per tile (single view), per
+// schedule item (batched grid), or persistent over items.
+template <int DT, bool kOne>
+__global__ void __launch_bounds__(kTilePix, kOne ? 3 : 2)
+render_dense_narrow_kernel(ViewArgs v, int n_tiles, int dim, qr_params prm) {
+  __shared__ DenseNarrowLds L;
+  dense_tile_narrow<DT, kOne>(to_global(v), xcd_remap(blockIdx.x, n_tiles), dim, prm, L);
+}
+
+template <int DT, bool kOne>
+__global__ void __launch_bounds__(kTilePix, kOne ? 3 : 2)
+render_dense_narrow_batched_grid_kernel(const qr_view* __restrict__ views,
+                                        const uint32_t* __restrict__ schedule, int n_items,
+                                        int dim, qr_params prm) {
+  __shared__ DenseNarrowLds L;
+  const int u = xcd_remap(blockIdx.x, n_items);
+  const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[u]);
+  const GView v = to_global(view_args(views[packed >> kViewShift]));
+  dense_tile_narrow<DT, kOne>(v, static_cast<int>(packed & kTileMask), dim, prm, L);
+}
+
+template <int DT, bool kOne>
+__global__ void __launch_bounds__(kTilePix, kOne ? 3 : 2)
+render_dense_narrow_batched_kernel(const qr_view* __restrict__ views,
+                                   const uint32_t* __restrict__ schedule, int64_t n_items,
+                                   uint32_t* __restrict__ counter, int dim, qr_params prm) {
+  __shared__ DenseNarrowLds L;
+  __shared__ uint32_t s_unit[2];
+  const int home = static_cast<int>(blockIdx.x % kDenseQueues);
+  for (int it = 0;; it ^= 1) {
+    if (threadIdx.x == 0) {
+      uint32_t unit = 0xFFFFFFFFu;
+      for (int d = 0; d < kDenseQueues; ++d) {
+        const int q = (home + d) % kDenseQueues;
+        const uint32_t b = dense_queue_begin(n_items, q), e = dense_queue_begin(n_items, q + 1);
+        if (b == e) continue;
+        const uint32_t i = atomicAdd(&counter[q], 1u);
+        if (i < e - b) {
+          unit = b + i;
+          break;
+        }
+      }
+      s_unit[it] = unit;
+    }
+    __syncthreads();
+    const uint32_t unit = __builtin_amdgcn_readfirstlane(s_unit[it]);
+    if (unit >= n_items) break;
+    const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[unit]);
+    const GView v = to_global(view_args(views[packed >> kViewShift]));
+    dense_tile_narrow<DT, kOne>(v, static_cast<int>(packed & kTileMask), dim, prm, L);
+  }
+}
+
 __global__ void reset_dense_counter_kernel(uint32_t* __restrict__ c) {
   if (threadIdx.x < kDenseQueues) c[threadIdx.x] = 0u;
 }
@@ -457,6 +746,19 @@ extern "C" int qr_render_dense(void* stream, int32_t width, int32_t height, cons
   const ViewArgs v{width, height, tile_offsets, sorted_gid, reinterpret_cast<const float2*>(means2d),
                    reinterpret_cast<const float4*>(conic_opacity), features, feature_scale, out,
                    T_final, n_contrib};
+  if (dim <= kGrpCols) {
+    const int nt = static_cast<int>(n_tiles);
+#define QR_LAUNCH(DT)                                                                           \
+  if (dim == 16)                                                                                \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(render_dense_narrow_kernel<DT, true>), dim3(nt),          \
+                       dim3(kTilePix), 0, s, v, nt, dim, *prm);                                 \
+  else                                                                                          \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(render_dense_narrow_kernel<DT, false>), dim3(nt),         \
+                       dim3(kTilePix), 0, s, v, nt, dim, *prm)
+    QR_DENSE_DISPATCH(dtype);
+#undef QR_LAUNCH
+    return check_launch("qr_render_dense");
+  }
 #define QR_LAUNCH(DT) \
   hipLaunchKernelGGL(render_dense_kernel<DT>, dim3(n_units), dim3(kTilePix), 0, s, v, n_units, dim, *prm)
   QR_DENSE_DISPATCH(dtype);
@@ -489,12 +791,20 @@ extern "C" int qr_render_dense_batched(void* stream, int32_t n_views, const qr_v
   if (prm->out_dtype != QR_F32) return fail(QR_ERR_UNSUPPORTED, "%s: float32 output only", name);
   if (n_items == 0) return QR_OK;
   hipStream_t s = as_stream(stream);
-  const int64_t n_units = n_items * kStrips;
+  const bool narrow = dim <= kGrpCols;  // one workgroup per item, else per (item, strip)
+  const int64_t n_units = narrow ? n_items : n_items * kStrips;
   if (n_workgroups == 0) {
     const int nu = static_cast<int>(n_units);
 #define QR_LAUNCH(DT)                                                                          \
-  hipLaunchKernelGGL(render_dense_batched_grid_kernel<DT>, dim3(nu), dim3(kTilePix), 0, s, views, \
-                     schedule, nu, dim, *prm)
+  if (narrow && dim == 16)                                                                     \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(render_dense_narrow_batched_grid_kernel<DT, true>),       \
+                       dim3(nu), dim3(kTilePix), 0, s, views, schedule, nu, dim, *prm);         \
+  else if (narrow)                                                                             \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(render_dense_narrow_batched_grid_kernel<DT, false>),      \
+                       dim3(nu), dim3(kTilePix), 0, s, views, schedule, nu, dim, *prm);         \
+  else                                                                                         \
+    hipLaunchKernelGGL(render_dense_batched_grid_kernel<DT>, dim3(nu), dim3(kTilePix), 0, s,    \
+                       views, schedule, nu, dim, *prm)
     QR_DENSE_DISPATCH(dtype);
 #undef QR_LAUNCH
     return check_launch(name);
@@ -502,8 +812,17 @@ extern "C" int qr_render_dense_batched(void* stream, int32_t n_views, const qr_v
   auto* counter = static_cast<uint32_t*>(workspace);
   hipLaunchKernelGGL(reset_dense_counter_kernel, dim3(1), dim3(64), 0, s, counter);
 #define QR_LAUNCH(DT)                                                                           \
-  hipLaunchKernelGGL(render_dense_batched_kernel<DT>, dim3(n_workgroups), dim3(kTilePix), 0, s,   \
-                     views, schedule, n_units, counter, dim, *prm)
+  if (narrow && dim == 16)                                                                      \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(render_dense_narrow_batched_kernel<DT, true>),             \
+                       dim3(n_workgroups), dim3(kTilePix), 0, s, views, schedule, n_units,       \
+                       counter, dim, *prm);                                                      \
+  else if (narrow)                                                                              \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(render_dense_narrow_batched_kernel<DT, false>),            \
+                       dim3(n_workgroups), dim3(kTilePix), 0, s, views, schedule, n_units,       \
+                       counter, dim, *prm);                                                      \
+  else                                                                                          \
+    hipLaunchKernelGGL(render_dense_batched_kernel<DT>, dim3(n_workgroups), dim3(kTilePix), 0, s, \
+                       views, schedule, n_units, counter, dim, *prm)
   QR_DENSE_DISPATCH(dtype);
 #undef QR_LAUNCH
   return check_launch(name);

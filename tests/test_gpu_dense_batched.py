@@ -1,6 +1,7 @@
-"""The dense blend (Eq. 1) on the strip kernel: single-view maps against the
-FP64 oracle at feature widths that leave partial column groups (16, 48,
-144) or need a second 512-column pass (528), with every feature storage;
+"""The dense blend (Eq. 1): single-view maps against the FP64 oracle at
+feature widths of the narrow tile kernels (16: one column tile; 48 and 64:
+one permuted group) and of the strip kernel (144: partial groups; 528: a
+second 512-column pass), with every feature storage;
 and the batched launch over (view, tile) items (every launch shape) bit for
 bit against the single-view kernel on views of uneven scenes and image
 shapes."""
@@ -27,7 +28,8 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("dim,storage", [(16, "f32"), (48, "f32"), (144, "f32"), (528, "f32"),
+@pytest.mark.parametrize("dim,storage", [(16, "f32"), (16, "bf16"), (16, "fp8"), (48, "f32"),
+                                         (48, "bf16"), (64, "fp8"), (144, "f32"), (528, "f32"),
                                          (144, "bf16"), (528, "fp8")])
 def test_dense_matches_oracle_feature_widths(qr, dim, storage):
     """100x75 (ragged tiles and strips that lie partly or wholly below the
@@ -69,7 +71,8 @@ def _make_views(qr, storage, dim):
     return views, single
 
 
-@pytest.mark.parametrize("storage,dim", [("f32", 32), ("f32", 528), ("bf16", 144), ("fp8", 64)])
+@pytest.mark.parametrize("storage,dim", [("f32", 16), ("bf16", 16), ("fp8", 16), ("f32", 32),
+                                         ("f32", 528), ("bf16", 144), ("fp8", 64)])
 def test_batched_dense_matches_single_view(qr, storage, dim):
     from paper_2512_20927_amd import _lib as L
     from paper_2512_20927_amd.batched import BatchedDense
