@@ -36,6 +36,7 @@
 // Widths up to 64 take the tile kernels further down (dense_tile_narrow):
 // one workgroup per tile, one sequential walk per pixel, one barrier per batch.
 #include "common.h"
+#include "dense_walk.h"
 #include "quantile_select.h"
 #include "render_common.h"
 
@@ -53,7 +54,7 @@ constexpr int kGrpCols = 64;                       // columns of a group (4 MFMA
 constexpr int kWaveGroups = 2;                     // groups per wave and pass
 constexpr int kPassCols = 4 * kWaveGroups * kGrpCols;  // 512 columns per pass
 constexpr int kWS = kDB + 8;                       // LDS row stride (bf16) of a pixel's weights
-constexpr uint32_t kStopBit = 0x100u;
+static_assert(kDB == kWalkBatch && kDQ == kWalkQ, "the strip's batches are the split walk's");
 
 struct DenseLds {
   __attribute__((aligned(16))) __bf16 whi[kStripPix * kWS];
@@ -66,7 +67,7 @@ struct DenseLds {
   __attribute__((aligned(16))) uint32_t gid[2][kDB];
   float part[4][kStripPix];   // product of (1 - alpha') over a wave's eight entries
   float tend[4][kStripPix];   // T after a wave's eight entries (before its stop)
-  uint32_t info[4][kStripPix];  // last blended entry (0..7, 0xFF none) | kStopBit
+  uint32_t info[4][kStripPix];  // walk_weights8's result word per wave
   unsigned long long busy[4];   // pixels with a non-zero weight, per wave
 };
 
@@ -277,76 +278,38 @@ __device__ void dense_strip(const GView& v, int tile, int strip, int dim, const 
       };
       load_group(0);
 
-      // walk, first half: alpha' of this wave's eight entries and the product
-      // of their (1 - alpha')
+      // walk (the split walk of dense_walk.h): alpha' of this wave's eight
+      // entries and the product of their (1 - alpha')
       float al[kDQ];
-      float part = 1.f;
-#pragma unroll
-      for (int j = 0; j < kDQ; ++j) {
-        const int e = kDQ * wave + j;
-        al[j] = 0.f;
-        if (e < cnt && !done) {
-          const float a = gauss_alpha(L.mean[e], L.co[e], pxc, pyc, prm.alpha_max);
-          if (a >= prm.alpha_min) {
-            al[j] = a;
-            part *= 1.f - a;
-          }
-        }
-      }
-      L.part[wave][lane] = part;
+      L.part[wave][lane] = walk_alpha8(L.mean, L.co, kDQ * wave, cnt, done, pxc, pyc, prm, al);
       __syncthreads();
 
-      // second half: T at the start of the eight entries, their weights in
-      // list order with the stop test
+      // T at the start of the eight entries, their weights in list order
+      // with the stop test
       float Tl = T;
       for (int q = 0; q < wave; ++q) Tl *= L.part[q][lane];
-      bool stopped = false;
-      uint32_t last = 0xFFu;
+      float w8[kDQ];
+      const uint32_t inf = walk_weights8(Tl, al, prm.T_eps, w8);
       bool any = false;
-      typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
-      bf16x8v whi, wlo;
+      bf16x8 whi, wlo;
 #pragma unroll
       for (int j = 0; j < kDQ; ++j) {
-        float w = 0.f;
-        if (al[j] > 0.f && !stopped) {
-          const float T_test = Tl * (1.f - al[j]);
-          if (T_test < prm.T_eps) {
-            stopped = true;
-          } else {
-            w = al[j] * Tl;
-            Tl = T_test;
-            last = static_cast<uint32_t>(j);
-          }
-        }
-        any |= w != 0.f;
+        any |= w8[j] != 0.f;
         __bf16 h, l;
-        split_bf16(w, h, l);
+        split_bf16(w8[j], h, l);
         whi[j] = h;
         wlo[j] = l;
       }
-      *reinterpret_cast<bf16x8v*>(&L.whi[lane * kWS + kDQ * wave]) = whi;
-      *reinterpret_cast<bf16x8v*>(&L.wlo[lane * kWS + kDQ * wave]) = wlo;
+      *reinterpret_cast<bf16x8*>(&L.whi[lane * kWS + kDQ * wave]) = whi;
+      *reinterpret_cast<bf16x8*>(&L.wlo[lane * kWS + kDQ * wave]) = wlo;
       L.tend[wave][lane] = Tl;
-      L.info[wave][lane] = last | (stopped ? kStopBit : 0u);
+      L.info[wave][lane] = inf;
       const unsigned long long b = __ballot(any);
       if (lane == 0) L.busy[wave] = b;
       __syncthreads();
 
-      // the pixel's state after the batch, folded in list order (the same in
-      // every wave)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (!done) {
-          const uint32_t inf = L.info[q][lane];
-          // T moves only with a blended entry (T_test >= T_eps), so it never
-          // falls below T_eps
-          if ((inf & 0xFFu) != 0xFFu) {
-            ncon = batch - lo + kDQ * q + static_cast<int>(inf & 0xFFu) + 1;
-            T = L.tend[q][lane];
-          }
-          if (inf & kStopBit) done = true;
-        }
-      }
+      // the pixel's state after the batch (the same in every wave)
+      walk_fold(&L.tend[0][0], &L.info[0][0], kStripPix, lane, batch - lo, T, done, ncon);
       const unsigned long long busy = L.busy[0] | L.busy[1] | L.busy[2] | L.busy[3];
       // the next batch's ids (its records are requested after the first
       // group's MFMAs, once the ids have arrived)
