@@ -458,6 +458,8 @@ def main():
         print("bench.py measures one GPU only: the renderer needs no exchange between GPUs "
               "and this build runs on a single MI355X; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.calib_copy:
+        calib_copy()
     {"room": run_room, "precision": run_precision, "diff": run_diff,
      "batched": run_batched, "devox": run_devox, "rgb": run_rgb}[args.workload](args)
 
@@ -474,14 +476,19 @@ def _scene_tensors(sc, torch):
     return dict(means=t(sc.means), scales=t(sc.scales), quats=t(sc.quats), opacity=t(sc.opacity))
 
 
+def calib_copy():
+    """A plain 1 GiB device copy (its counted traffic calibrates FETCH_SIZE and
+    WRITE_SIZE)."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def run_room(args):
     import torch
-    if args.calib_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     import paper_2512_20927_amd as qr
     from paper_2512_20927_amd import _lib as L
     from paper_2512_20927_amd.batched import autotune

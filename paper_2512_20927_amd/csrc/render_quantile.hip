@@ -16,9 +16,8 @@
 // from L2: neighbouring pixels select the same Gaussians); rows are
 // accumulated in float32 and streamed to the [H, W, D] map with non-temporal
 // stores. The map write is the dominant HBM traffic of the whole pipeline.
-// The walk and the merge are wave-local (wave w's pixels are tile rows
-// 4w .. 4w+3, whose groups it merges); narrow rows are gathered by the same
-// wave, wide rows one tile row at a time by all four waves after a barrier.
+// Everything after the walk is wave-local: wave w's pixels (tile rows
+// 4w .. 4w+3) are exactly the pixels of the groups it gathers.
 #include "quantile_select.h"
 
 namespace qr {
@@ -291,10 +290,10 @@ __device__ __forceinline__ void gather_group_per_pixel(const GView& v, const Lds
 
 // Algorithm 1 for every pixel of one tile, then the gather-blend of the
 // selected rows. Called by all 256 threads of the workgroup. Workgroup
-// barriers occur around the staging of record batches and, for wide rows,
-// between the merge and the gather; the pixels of wave w are tile rows
-// 4w .. 4w+3, whose groups it merges. Shared LDS (the record batch, the
-// selections and merged groups) is only rewritten after a barrier that every
+// barriers occur only around the staging of record batches; the pixels of
+// wave w are tile rows 4w .. 4w+3, which are exactly the pixels of the
+// gather groups it owns, so everything after the walk is wave-local.
+// Shared LDS (the record batch) is only rewritten after a barrier that every
 // wave reaches once it has finished the previous tile.
 template <int DT, int OT, int MODE, class Lds>
 __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, int dim,
@@ -330,15 +329,8 @@ __device__ __forceinline__ void quantile_tile(const GView& v, int tile, int K, i
     gather_groups_narrow<DT, OT>(v, L, wave, tx, ty, lane, dim);
     gather_groups_narrow_overflow<DT, OT>(v, L, s_sel_pos, s_sel_w, KP, K, wave, tx, ty, lane, dim);
   } else {
-    // Wide rows: the four waves write one tile row at a time (wave w takes
-    // its 4-pixel segment w), so the workgroup's stores at any moment are one
-    // contiguous 32 KB run of the map, and neighbouring tiles in flight on an
-    // XCD write adjacent runs; the merged groups of the other waves' rows are
-    // read after this barrier. The next tile's walk rewrites them only after
-    // the barrier every wave reaches before it.
-    __syncthreads();
     for (int gl = 0; gl < kWaveGroups; ++gl) {
-      const int grp = gl * 4 + wave;
+      const int grp = wave * kWaveGroups + gl;
       const int nu = __builtin_amdgcn_readfirstlane(L.unum[grp]);
       if (nu >= 0)
         gather_group_merged<DT, OT>(v, L, grp, nu, tx, ty, lane, dim);

@@ -39,9 +39,20 @@ KERNEL_SOURCES = {
                         "paper_2512_20927_amd/csrc/render_common.h",
                         "paper_2512_20927_amd/csrc/common.h"],
     "render_dense": ["paper_2512_20927_amd/csrc/render_dense.hip",
+                     "paper_2512_20927_amd/csrc/dense_walk.h",
                      "paper_2512_20927_amd/csrc/quantile_select.h",
                      "paper_2512_20927_amd/csrc/render_common.h",
                      "paper_2512_20927_amd/csrc/common.h"],
+    "dense_backward": ["paper_2512_20927_amd/csrc/render_backward.hip",
+                       "paper_2512_20927_amd/csrc/dense_walk.h",
+                       "paper_2512_20927_amd/csrc/wave_ops.h",
+                       "paper_2512_20927_amd/csrc/render_common.h",
+                       "paper_2512_20927_amd/csrc/common.h"],
+    "quantile_backward": ["paper_2512_20927_amd/csrc/render_quantile_backward.hip",
+                          "paper_2512_20927_amd/csrc/quantile_select.h",
+                          "paper_2512_20927_amd/csrc/wave_ops.h",
+                          "paper_2512_20927_amd/csrc/render_common.h",
+                          "paper_2512_20927_amd/csrc/common.h"],
 }
 
 COPY_BYTES = 1 << 30
