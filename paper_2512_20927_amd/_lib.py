@@ -14,10 +14,8 @@ import os
 
 import torch
 
-# QRENDER_LIB selects another build of the same library (e.g. to compare two
-# builds side by side); by default the in-tree build is loaded.
-LIB_PATH = os.environ.get("QRENDER_LIB") or os.path.join(
-    os.path.dirname(os.path.abspath(__file__)), "libqrender.so")
+# the in-tree build (paper_2512_20927_amd/build.py)
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libqrender.so")
 
 QR_OK, QR_ERR_INVALID_ARG, QR_ERR_UNSUPPORTED, QR_ERR_CAPACITY, QR_ERR_HIP = 0, -1, -2, -3, -4
 QR_F32, QR_BF16, QR_FP8_E4M3 = 0, 1, 2
