@@ -202,9 +202,11 @@ __device__ __forceinline__ void slot_dots(const GView& v, const GGrad& gg, const
 }
 
 // dF[s][c] = sum_p (w_ps / Z_p) g_p[c] for the tile's slots and this wave's
-// column blocks (16-column block b belongs to wave b % 4, kNB of them per
-// round), added to grad_features. The dL/d(out) operand of step k+1 is
-// requested before step k is multiplied.
+// column blocks, added to grad_features. A wave takes kNB consecutive
+// 16-column blocks per round (blocks 4 kNB r + kNB wave .. + kNB - 1 in round
+// r), so its loads of one pixel row cover whole 128-byte lines instead of the
+// halves that alternating waves would request at different times. The
+// dL/d(out) operand of step k+1 is requested before step k is multiplied.
 __device__ __forceinline__ void slot_feature_grads(const GView& v, const GGrad& gg, const BwdLds& B,
                                                    const float* __restrict__ s_sel_w, int nslot,
                                                    int tx, int ty, int wave, int lane, int dim,
@@ -213,7 +215,7 @@ __device__ __forceinline__ void slot_feature_grads(const GView& v, const GGrad& 
   const int n_mb = (nslot + 15) >> 4;
   const int n_blk = dim >> 4;
   constexpr int kSteps = kTilePix / 32;
-  for (int b0 = wave; b0 < n_blk; b0 += 4 * kNB) {
+  for (int b0 = wave * kNB; b0 < n_blk; b0 += 4 * kNB) {
     floatx4 acc[2][kNB];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
@@ -221,7 +223,7 @@ __device__ __forceinline__ void slot_feature_grads(const GView& v, const GGrad& 
       for (int nb = 0; nb < kNB; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
     int col[kNB];
 #pragma unroll
-    for (int nb = 0; nb < kNB; ++nb) col[nb] = min(b0 + 4 * nb, n_blk - 1) * 16 + row;  // clamped
+    for (int nb = 0; nb < kNB; ++nb) col[nb] = min(b0 + nb, n_blk - 1) * 16 + row;  // clamped
     // B = G: pixels k*32 + kq .. + 7, column col[nb]
     auto load = [&](int k, float (&x)[kNB][8]) {
 #pragma unroll
@@ -278,7 +280,7 @@ __device__ __forceinline__ void slot_feature_grads(const GView& v, const GGrad& 
         QR_GLOBAL float* dst = gg.grad_features + static_cast<int64_t>(B.sgid[sl]) * dim + row;
 #pragma unroll
         for (int nb = 0; nb < kNB; ++nb) {
-          const int blk = b0 + 4 * nb;
+          const int blk = b0 + nb;
           if (blk < n_blk && acc[mb][nb][i] != 0.f) atomic_add(dst + blk * 16, acc[mb][nb][i]);
         }
       }
