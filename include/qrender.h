@@ -26,6 +26,9 @@
  *    qr_last_error() returns a message describing the last failure of the
  *    calling thread.
  *  - Arrays are dense and row-major; "f32[N,4]" is N rows of 4 floats.
+ *    Device arrays are expected to start on a 16-byte boundary (hipMalloc
+ *    and torch allocations do): feature tables, maps and gradient maps are
+ *    read and written with 16-byte vector accesses.
  *  - Screen tiles are 16 x 16 pixels, tile id = ty * tiles_x + tx with
  *    tiles_x = ceil(W / 16), tiles_y = ceil(H / 16). Pixel (px, py) is
  *    sampled at its centre (px + 0.5, py + 0.5). Feature maps are pixel-major

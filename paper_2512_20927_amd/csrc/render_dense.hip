@@ -265,11 +265,12 @@ __device__ void dense_strip(const GView& v, int tile, int strip, int dim, const 
       // feature rows of the batch for this wave's first group, requested now
       // so that the loads overlap the walk (the second group's are requested
       // before the first group's MFMAs). No branches: ids past the list are
-      // valid rows (weight 0), and columns past the width of a partial group
-      // are clamped to its first (their results are never stored).
+      // valid rows (weight 0), columns past the width of a partial group are
+      // clamped to its first, and a group past the width (no MFMAs, nothing
+      // stored) reads column 0 (their results are never stored).
       f32x4 raw[8];
       const auto load_group = [&](int k) {
-        const int col = gbase[k] + (coff < gw[k] ? coff : 0);
+        const int col = gw[k] > 0 ? gbase[k] + (coff < gw[k] ? coff : 0) : 0;
         const u32x4 ga = *reinterpret_cast<const u32x4*>(&gid[8 * kb]);
         const u32x4 gb = *reinterpret_cast<const u32x4*>(&gid[8 * kb + 4]);
         const uint32_t g8[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
