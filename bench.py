@@ -217,13 +217,18 @@ def dense_list_prefix(b, n_contrib, W, H):
     return total, int(torch.unique(b.sorted_gid[idx]).numel())
 
 
-def measured_traffic(kernel, workload, family="render_quantile"):
+def measured_traffic(kernel, workload, family="render_quantile", summary=None):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE passes, calibrated by a 1 GiB copy), or None when
-    there is none or the kernel's sources changed since it was taken."""
+    there is none or the kernel's sources changed since it was taken.
+    summary: a file of several kernels' blocks (else <kernel>_<workload>_pmc.txt)."""
     from paper_2512_20927_amd import profile_summary as ps
-    name = kernel.split("<")[0].replace("_kernel", "")
-    info = ps.read_summary(os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (name, workload)))
+    name = kernel.split("<")[0]
+    if summary is None:
+        info = ps.read_summary(os.path.join(ROOT, "profiles", "%s_%s_pmc.txt"
+                                            % (name.replace("_kernel", ""), workload)))
+    else:
+        info = ps.read_summary(os.path.join(ROOT, "profiles", summary), kernel=name)
     if not info or info.get("source_sha256") != ps.source_hash(family):
         return None
     return int(info["traffic_bytes_per_launch"])
@@ -856,7 +861,67 @@ def run_diff(args):
                        "backward (autograd, cosine loss); one iteration = one view",
                        1e3 / res["q"])
     rec.update({"dense_value": round(res["d"], 2), "q_over_dense": round(res["q"] / res["d"], 3)})
+    rec.update(backward_kernels(args, qr, s, cam, pr, binner, storage, target, W, H, K, prm))
     print(json.dumps(rec))
+
+
+def backward_kernels(args, qr, s, cam, pr, binner, storage, target, W, H, K, prm):
+    """The two backward calls alone on one frame of the diff workload (after
+    the timed iterations): each timed over `steps` calls with HIP events on
+    the launch stream, with dL/d(out) of the same cosine loss. The Q-Render
+    backward's roofline takes the algorithmic bytes of one frame: dL/d(out)
+    read once, the view's distinct selected rows read (bf16) and their
+    float32 gradients read and written, 28 B of records per entry of the
+    whole tile lists (an upper bound: the walk stops early in most tiles)."""
+    import torch
+    from paper_2512_20927_amd import _lib as L
+    qr.project(s["means"], s["scales"], s["quats"], s["opacity"], cam, out=pr)
+    bins = binner(pr)
+    feats = storage[0]
+    n, D = feats.shape
+    r = qr.render_quantile(pr, bins, feats, W, H, K, prm, debug=True)
+    g = r["sel_gid"]
+    uniq = int(torch.unique(g[g >= 0]).numel())
+    pairs = int(bins.tile_offsets[-1].item() - bins.tile_offsets[0].item())
+    d = qr.render_dense(pr, bins, feats, W, H, prm)
+
+    def grad_of(out):
+        o = out.detach().requires_grad_(True)
+        loss = (1 - torch.nn.functional.cosine_similarity(o, target, dim=-1)).mean()
+        return torch.autograd.grad(loss, o)[0].contiguous()
+
+    gq, gd = grad_of(r["out"]), grad_of(d["out"])
+    gf = torch.zeros(n, D, device="cuda")
+    gm = torch.zeros(n, 2, device="cuda")
+    gc = torch.zeros(n, 4, device="cuda")
+    calls = {
+        "quantile": lambda: L.qr_render_quantile_backward(
+            W, H, prm.c(), K, bins.tile_offsets, bins.sorted_gid, pr.means2d, pr.conic_opacity,
+            feats, None, gq, gf, gm, gc),
+        "dense": lambda: L.qr_render_dense_backward(
+            W, H, prm.c(), bins.tile_offsets, bins.sorted_gid, pr.means2d, pr.conic_opacity,
+            feats, None, d["out"], gd, gf, gm, gc),
+    }
+    ms = {}
+    for name, call in calls.items():
+        for _ in range(max(args.warmup, 1)):
+            call()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.steps):
+            call()
+        b.record()
+        torch.cuda.synchronize()
+        ms[name] = a.elapsed_time(b) / args.steps
+    nbytes = H * W * D * 4 + uniq * D * (2 + 8) + pairs * 28
+    achieved = nbytes / (ms["quantile"] * 1e-3) / 1e9
+    return {"backward_ms": {k: round(v, 4) for k, v in ms.items()},
+            "backward_roofline": {
+                "bound": "hbm", "kernel": "quantile_backward_kernel<1>", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic("quantile_backward_kernel", "diff", "quantile_backward",
+                                            summary="backward_diff_pmc.txt"),
+                "bytes_per_launch": nbytes, "selected_unique": uniq, "pairs": pairs}}
 
 
 def run_devox(args):

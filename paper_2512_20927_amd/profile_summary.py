@@ -144,13 +144,18 @@ def counters(path: str, kernel: str) -> str:
     return "\n".join(out)
 
 
-def read_summary(path: str) -> dict:
-    """key: value lines of a summary file (other lines ignored)."""
+def read_summary(path: str, kernel: str | None = None) -> dict:
+    """key: value lines of a summary file (other lines ignored). With
+    `kernel`, only the block that starts with "kernel: <kernel>" (files that
+    summarise several kernels)."""
     out = {}
     if not os.path.exists(path):
         return out
+    inside = kernel is None
     for line in open(path):
-        if ":" in line and not line.startswith(" "):
+        if kernel is not None and line.startswith("kernel:"):
+            inside = line.split(":", 1)[1].strip() == kernel
+        if inside and ":" in line and not line.startswith(" "):
             k, v = line.split(":", 1)
             out[k.strip()] = v.strip()
     return out
