@@ -144,8 +144,8 @@ __device__ __forceinline__ void slot_dots(const GView& v, const GGrad& gg, const
     const int c = min(k * 32 + kq, dim - 8);  // dim is a multiple of 8
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
-      o.a[mb][0] = __builtin_nontemporal_load(reinterpret_cast<const QR_GLOBAL f32x4*>(arow[mb] + c));
-      o.a[mb][1] = __builtin_nontemporal_load(reinterpret_cast<const QR_GLOBAL f32x4*>(arow[mb] + c + 4));
+      o.a[mb][0] = *reinterpret_cast<const QR_GLOBAL f32x4*>(arow[mb] + c);
+      o.a[mb][1] = *reinterpret_cast<const QR_GLOBAL f32x4*>(arow[mb] + c + 4);
     }
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) load_feat8<DT>(v, gid[nb], dim, c, o.f[nb]);
@@ -224,13 +224,15 @@ __device__ __forceinline__ void slot_feature_grads(const GView& v, const GGrad& 
     int col[kNB];
 #pragma unroll
     for (int nb = 0; nb < kNB; ++nb) col[nb] = min(b0 + nb, n_blk - 1) * 16 + row;  // clamped
-    // B = G: pixels k*32 + kq .. + 7, column col[nb]
+    // B = G: pixels k*32 + kq .. + 7, column col[nb]. Plain (caching) loads:
+    // the dots pass reads the same rows next and finds them in the caches
+    // (with non-temporal loads the backward took 8% longer).
     auto load = [&](int k, float (&x)[kNB][8]) {
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const QR_GLOBAL float* r = grad_row(v, gg, tx, ty, k * 32 + kq + t, dim);
 #pragma unroll
-        for (int nb = 0; nb < kNB; ++nb) x[nb][t] = __builtin_nontemporal_load(r + col[nb]);
+        for (int nb = 0; nb < kNB; ++nb) x[nb][t] = r[col[nb]];
       }
     };
     auto multiply = [&](int k, const float (&x)[kNB][8]) {
