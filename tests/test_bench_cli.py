@@ -52,3 +52,23 @@ def test_oracle_tile_equals_the_full_frame_render():
         np.testing.assert_array_equal(q["out"], full_q["out"][y0:y0 + h, x0:x0 + w])
         np.testing.assert_array_equal(q["margin"], full_q["margin"][y0:y0 + h, x0:x0 + w])
         np.testing.assert_array_equal(d["out"], full_d["out"][y0:y0 + h, x0:x0 + w])
+
+
+def test_counter_summary_blocks_and_source_hash(tmp_path, monkeypatch):
+    """A summary file of several kernels: each kernel's traffic comes from
+    its own block, and a block whose source hash no longer matches the
+    sources gives no traffic."""
+    import bench
+    from paper_2512_20927_amd import profile_summary as ps
+    cur = ps.source_hash("quantile_backward")
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "two_pmc.txt").write_text(
+        "# header: ignored\n\n"
+        "kernel: first_kernel\ntraffic_bytes_per_launch: 111\nsource_sha256: %s\n\n"
+        "kernel: second_kernel\ntraffic_bytes_per_launch: 222\nsource_sha256: %s\n" % (cur, "0" * 16))
+    got = ps.read_summary(str(tmp_path / "profiles" / "two_pmc.txt"), kernel="first_kernel")
+    assert got["traffic_bytes_per_launch"] == "111" and got["source_sha256"] == cur
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("first_kernel<1>", "x", "quantile_backward", summary="two_pmc.txt") == 111
+    assert bench.measured_traffic("second_kernel", "x", "quantile_backward", summary="two_pmc.txt") is None
+    assert bench.measured_traffic("third_kernel", "x", "quantile_backward", summary="two_pmc.txt") is None
