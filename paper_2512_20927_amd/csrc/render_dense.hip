@@ -190,9 +190,19 @@ __device__ __forceinline__ void store_group(const GView& v, const f32x4 (&acc)[4
 // One 64-pixel strip of one tile: Eq. 1 for its pixels, all `dim` columns.
 // Called by all 256 threads; every barrier is reached by every wave the same
 // number of times (loop bounds and exits are uniform over the workgroup).
-template <int DT>
+// rgid, rmean, rco: threads 0..31 carry the records of the batch being
+// requested (with `preloaded`, the caller has already requested the first
+// batch's); before_stores is called by every thread once, right before the
+// map stores of the last pass (a persistent caller requests its next unit's
+// first records there: a load issued after a store waits for it).
+struct NoHook {
+  __device__ void operator()() const {}
+};
+
+template <int DT, class Hook = NoHook>
 __device__ void dense_strip(const GView& v, int tile, int strip, int dim, const qr_params& prm,
-                            DenseLds& L) {
+                            DenseLds& L, int& rgid, f32x2& rmean, f32x4& rco, bool preloaded,
+                            const Hook& before_stores = Hook()) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -213,10 +223,6 @@ __device__ void dense_strip(const GView& v, int tile, int strip, int dim, const 
   // The next batch's ids and records are requested by threads 0..31 while
   // the current batch is contracted, and staged into LDS at the top of the
   // next iteration.
-  int rgid = -1;
-  f32x2 rmean = f32x2{0.f, 0.f};
-  f32x4 rco = f32x4{0.f, 0.f, 0.f, 0.f};
-
   for (int c0 = 0; c0 < dim; c0 += kPassCols) {
     // this wave's column groups in the pass: base column and width (0: none)
     int gbase[kWaveGroups], gw[kWaveGroups];
@@ -238,7 +244,7 @@ __device__ void dense_strip(const GView& v, int tile, int strip, int dim, const 
 
     // the pixel states are identical in every wave: uniform exits
     const bool first = lo < hi && __ballot(!done) != 0ull;  // uniform
-    if (first && tid < kDB && lo + tid < hi) {
+    if (first && tid < kDB && lo + tid < hi && !(preloaded && c0 == 0)) {
       rgid = static_cast<int>(v.sorted_gid[lo + tid]);
       rmean = v.means2d[rgid];
       rco = v.conic_opacity[rgid];
@@ -337,6 +343,7 @@ __device__ void dense_strip(const GView& v, int tile, int strip, int dim, const 
       }
     }
 
+    if (c0 + kPassCols >= dim) before_stores();
 #pragma unroll
     for (int k = 0; k < kWaveGroups; ++k)
       if (gw[k] > 0) store_group(v, acc[k], tx, ty, strip, gbase[k], gw[k], dim, ci, kb);
@@ -567,7 +574,10 @@ __global__ void __launch_bounds__(kTilePix, 2)
 render_dense_kernel(ViewArgs v, int n_units, int dim, qr_params prm) {
   __shared__ DenseLds L;
   const int u = xcd_remap(blockIdx.x, n_units);
-  dense_strip<DT>(to_global(v), u / kStrips, u % kStrips, dim, prm, L);
+  int rgid = -1;
+  f32x2 rmean = f32x2{0.f, 0.f};
+  f32x4 rco = f32x4{0.f, 0.f, 0.f, 0.f};
+  dense_strip<DT>(to_global(v), u / kStrips, u % kStrips, dim, prm, L, rgid, rmean, rco, false);
 }
 
 // Many views, one workgroup per (item, strip) unit of the schedule.
@@ -580,7 +590,11 @@ render_dense_batched_grid_kernel(const qr_view* __restrict__ views,
   const int u = xcd_remap(blockIdx.x, n_units);
   const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[u / kStrips]);
   const GView v = to_global(view_args(views[packed >> kViewShift]));
-  dense_strip<DT>(v, static_cast<int>(packed & kTileMask), u % kStrips, dim, prm, L);
+  int rgid = -1;
+  f32x2 rmean = f32x2{0.f, 0.f};
+  f32x4 rco = f32x4{0.f, 0.f, 0.f, 0.f};
+  dense_strip<DT>(v, static_cast<int>(packed & kTileMask), u % kStrips, dim, prm, L, rgid, rmean, rco,
+                  false);
 }
 
 // Many views, persistent workgroups over (item, strip) units through one
@@ -600,28 +614,60 @@ render_dense_batched_kernel(const qr_view* __restrict__ views, const uint32_t* _
   __shared__ DenseLds L;
   __shared__ uint32_t s_unit[2];
   const int home = static_cast<int>(blockIdx.x % kDenseQueues);
-  for (int it = 0;; it ^= 1) {
-    if (threadIdx.x == 0) {
-      uint32_t unit = 0xFFFFFFFFu;
-      for (int d = 0; d < kDenseQueues; ++d) {
-        const int q = (home + d) % kDenseQueues;
-        const uint32_t b = dense_queue_begin(n_units, q), e = dense_queue_begin(n_units, q + 1);
-        if (b == e) continue;
-        const uint32_t i = atomicAdd(&counter[q], 1u);
-        if (i < e - b) {
-          unit = b + i;
-          break;
-        }
+  const auto claim = [&]() {
+    uint32_t unit = 0xFFFFFFFFu;
+    for (int d = 0; d < kDenseQueues; ++d) {
+      const int q = (home + d) % kDenseQueues;
+      const uint32_t b = dense_queue_begin(n_units, q), e = dense_queue_begin(n_units, q + 1);
+      if (b == e) continue;
+      const uint32_t i = atomicAdd(&counter[q], 1u);
+      if (i < e - b) {
+        unit = b + i;
+        break;
       }
-      s_unit[it] = unit;
     }
+    return unit;
+  };
+  if (threadIdx.x == 0) s_unit[0] = claim();
+  // the first records of the next unit, requested by wave 0 before the
+  // current unit's map stores (a load issued after a store waits for it)
+  int rgid = -1;
+  f32x2 rmean = f32x2{0.f, 0.f};
+  f32x4 rco = f32x4{0.f, 0.f, 0.f, 0.f};
+  bool preloaded = false;
+  for (int it = 0;; it ^= 1) {
     __syncthreads();
     const uint32_t unit = __builtin_amdgcn_readfirstlane(s_unit[it]);
     if (unit >= n_units) break;
     const uint32_t packed = __builtin_amdgcn_readfirstlane(schedule[unit / kStrips]);
     const GView v = to_global(view_args(views[packed >> kViewShift]));
+    const int slot = it ^ 1;
+    const auto before_stores = [&]() {
+      uint32_t next = 0xFFFFFFFFu;
+      if (threadIdx.x == 0) {
+        next = claim();
+        s_unit[slot] = next;
+      }
+      preloaded = false;
+      if (threadIdx.x < 64) {
+        const uint32_t nu = __builtin_amdgcn_readfirstlane(next);
+        if (nu < n_units) {
+          const uint32_t np = __builtin_amdgcn_readfirstlane(schedule[nu / kStrips]);
+          const GView nv = to_global(view_args(views[np >> kViewShift]));
+          const int nt = static_cast<int>(np & kTileMask);
+          const int lo = static_cast<int>(nv.tile_offsets[nt]);
+          const int hi = static_cast<int>(nv.tile_offsets[nt + 1]);
+          if (threadIdx.x < kDB && lo + static_cast<int>(threadIdx.x) < hi) {
+            rgid = static_cast<int>(nv.sorted_gid[lo + threadIdx.x]);
+            rmean = nv.means2d[rgid];
+            rco = nv.conic_opacity[rgid];
+          }
+          preloaded = true;
+        }
+      }
+    };
     dense_strip<DT>(v, static_cast<int>(packed & kTileMask), static_cast<int>(unit % kStrips), dim,
-                    prm, L);
+                    prm, L, rgid, rmean, rco, preloaded, before_stores);
   }
 }
 
