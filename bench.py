@@ -862,8 +862,34 @@ def run_diff(args):
                        1e3 / res["q"])
     rec.update({"dense_value": round(res["d"], 2), "q_over_dense": round(res["q"] / res["d"], 3)})
     rec.update(backward_kernels(args, qr, s, cam, pr, binner, storage, target, W, H, K, prm))
+    if args.cpu_budget > 0 and not args.renders_only:
+        rec["cpu_baseline"] = fd_cpu_baseline(args, qr, K)
     print(json.dumps(rec))
 
+
+def fd_cpu_baseline(args, qr, K):
+    """The FP64 oracle on one core over the 2,000-Gaussian 32x32 512-D
+    finite-difference sub-case: projection, binning, one Q-Render forward and
+    its analytic backward (about 5 s). The sample is not the 640x480 frame of
+    `value`; it is timed as the oracle stands, on the host only."""
+    import oracle
+    import synth
+    from threadpoolctl import threadpool_limits
+    sc, cam = synth.make_fd_case(seed=5)
+    gout = np.random.default_rng(99).standard_normal((32, 32, sc.dim))
+    t0 = time.perf_counter()
+    with threadpool_limits(1):
+        prm_o = oracle.RenderParams()
+        pr_o = oracle.project(sc.means, sc.scales, sc.quats, sc.opacity, cam, prm_o)
+        gids, offs, _ = oracle.bin_sort(pr_o["rect"], pr_o["depth"], 2, 2)
+        proj = dict(means2d=pr_o["means2d"], conic=pr_o["conic"], opacity=pr_o["opacity"])
+        oracle.render_quantile(proj, gids, offs, sc.features, 32, 32, K, prm_o)
+        oracle.quantile_backward(proj, gids, offs, sc.features, 32, 32, K, gout, prm_o)
+    dt = time.perf_counter() - t0
+    return {"value": round(1.0 / dt, 4), "unit": "iterations/s", "cores": 1, "kind": "oracle",
+            "sample": "the 2,000-Gaussian 32x32 512-D finite-difference sub-case: projection, "
+                      "binning, one Q-Render K=%d forward and its analytic backward in FP64 "
+                      "(%.1f s); not the 640x480 frame that `value` measures" % (K, dt)}
 
 def backward_kernels(args, qr, s, cam, pr, binner, storage, target, W, H, K, prm):
     """The two backward calls alone on one frame of the diff workload (after
